@@ -1,0 +1,91 @@
+"""Diagnostics for the DG oracle: energy, its exact dissipation, errors, the
+assembled operator and the time-step rule.  Test infrastructure only.
+
+Energy: E(u) = 1/2 sum_k J_k u_k^T (M (x) I_6) u_k, the M^k-norm of the
+global-matrix definitions (Section 2) with M^k = J_k M (Section 2.1).
+
+Dissipation: for the scheme and flux of ``oracle.maxwell`` the discrete
+energy rate is exactly
+    sum_k J_k u^T M rhs_k = - alpha/2 sum_{interior faces} [ |n x dE|^2 + |n x dH|^2 ]_f
+                            - alpha   sum_{wall faces}     [ |n x E-|^2 ]_f,
+where [g]_f = sJ_f sum_c g_c^T M_f g_c integrates over the face with the face
+mass matrix (derived from the divergence of E x H, the central part of the
+flux cancelling between the two sides of every interior face).
+``dissipation`` evaluates the right side from traces only.
+
+Parity: ``energy``/``dissipation`` are pinned against each other through the
+oracle RHS (tests/test_oracle_rhs.py) and by alpha = 0 giving exactly 0;
+``assemble`` is a column-by-column application of the RHS.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .maxwell import rhs, traces
+
+
+def energy(mesh, u):
+    u = np.asarray(u, dtype=np.float64)
+    Mu = u @ mesh.re.M.T                               # (6, K, Np)
+    return 0.5 * float(np.sum(mesh.J[None, :, None] * u * Mu))
+
+
+def energy_rate(mesh, u, alpha: float = 1.0):
+    """sum_k J_k u^T M rhs_k computed through the oracle RHS."""
+    r = rhs(mesh, u, alpha)
+    Mr = r @ mesh.re.M.T
+    return float(np.sum(mesh.J[None, :, None] * u * Mr))
+
+
+def dissipation(mesh, u, alpha: float = 1.0):
+    """Right side of the energy identity, from face traces only."""
+    uM, uP, bnd = traces(mesh, u)
+    n = np.stack([mesh.nx, mesh.ny, mesh.nz])[:, :, :, None]
+    Mf = mesh.re.Mf                                      # (4, Nfp, Nfp)
+
+    def face_form(g):
+        # g: (3, K, 4, Nfp) -> (K, 4) sum_c g_c^T M_f g_c
+        Mg = np.einsum("fij,ckfj->ckfi", Mf, g)
+        return np.sum(g * Mg, axis=(0, 3))
+
+    ncdE = np.cross(n, uM[0:3] - uP[0:3], axis=0)
+    ncdH = np.cross(n, uM[3:6] - uP[3:6], axis=0)
+    ncE = np.cross(n, uM[0:3], axis=0)
+    interior = ~bnd
+    fi = face_form(ncdE) + face_form(ncdH)
+    fb = face_form(ncE)
+    total = -0.5 * alpha * np.sum((mesh.sJ * fi)[interior]) * 0.5  # each interior face seen twice
+    total += -alpha * np.sum((mesh.sJ * fb)[bnd])
+    return float(total)
+
+
+def mass_norm(mesh, u):
+    return float(np.sqrt(2.0 * energy(mesh, u)))
+
+
+def assemble(mesh, alpha: float = 1.0):
+    """Dense operator matrix A with rhs(u).ravel() = A @ u.ravel() (tiny meshes only)."""
+    n = 6 * mesh.K * mesh.Np
+    Amat = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[j] = 1.0
+        Amat[:, j] = rhs(mesh, e.reshape(6, mesh.K, mesh.Np), alpha).ravel()
+        e[j] = 0.0
+    return Amat
+
+
+def block_mass(mesh):
+    """Diagonal-block global mass matrix (M^k (x) I_6) matching u.ravel() order."""
+    n = 6 * mesh.K * mesh.Np
+    W = np.zeros((n, n))
+    for c in range(6):
+        for k in range(mesh.K):
+            o = (c * mesh.K + k) * mesh.Np
+            W[o:o + mesh.Np, o:o + mesh.Np] = mesh.J[k] * mesh.re.M
+    return W
+
+
+def dt_cfl(mesh, cfl: float = 0.5):
+    """Time step reading dt = CFL * 2 / ((N+1)^2 * max Fscale)  (dt ~ dx / N^2)."""
+    return cfl * 2.0 / ((mesh.N + 1) ** 2 * float(np.max(mesh.Fscale)))

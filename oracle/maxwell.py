@@ -1,0 +1,89 @@
+"""Semi-discrete nodal DG right-hand side for 3D Maxwell (FP64, NumPy).  Test infrastructure only.
+
+The operator is the paper's semi-discrete scheme (Section 2):
+    du/dt = - sum_nu D^nu F(u) + L [ n.F - (n.F)* ]   on every element,
+for the linear Maxwell flux, split as in Section 2.1 into F(u), local
+differentiation, flux gather and flux lifting.  With eps = mu = 1 and
+u = (E, H):  dE/dt = curl H, dH/dt = -curl E, so -D F(u) is the discrete curl
+built from the reference Dr, Ds, Dt and the element's constant metric.
+
+Flux (results section, Maxwell upwind flux; H part by E -> H, H -> -E
+duality), with jumps dE = E- - E+, dH = H- - H+:
+    fE = 1/2 [ -n x dH + alpha (n (n . dE) - dE) ]
+    fH = 1/2 [  n x dE + alpha (n (n . dH) - dH) ]
+and rhs += LIFT (Fscale * f).  Perfectly conducting walls use the mirror
+state E+ = -E-, H+ = H-, i.e. dE = 2 E-, dH = 0.  alpha = 1 is upwind,
+alpha = 0 central.
+
+The sign reading (the printed flux is the term subtracted, i.e. the
+n.F - (n.F)* of the scheme equals the expression above) is the one under which
+the discrete energy is non-increasing; tests/test_oracle_rhs.py pins it by
+the exact discrete energy identity.
+
+Layout: u is (6, K, Np) FP64 in the field order (Ex, Ey, Ez, Hx, Hy, Hz).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def curl(mesh, fx, fy, fz):
+    """Discrete curl of a nodal vector field (each (K, Np))."""
+    re = mesh.re
+
+    def grads(f):
+        fr = f @ re.Dr.T
+        fs = f @ re.Ds.T
+        ft = f @ re.Dt.T
+        dx = mesh.rx[:, None] * fr + mesh.sx[:, None] * fs + mesh.tx[:, None] * ft
+        dy = mesh.ry[:, None] * fr + mesh.sy[:, None] * fs + mesh.ty[:, None] * ft
+        dz = mesh.rz[:, None] * fr + mesh.sz[:, None] * fs + mesh.tz[:, None] * ft
+        return dx, dy, dz
+
+    xx, xy, xz = grads(fx)
+    yx, yy, yz = grads(fy)
+    zx, zy, zz = grads(fz)
+    return zy - yz, xz - zx, yx - xy
+
+
+def traces(mesh, u):
+    """Interior and exterior traces at face nodes, each (6, K, 4, Nfp), and the
+    boundary mask (K, 4)."""
+    K, Np, Nfp = mesh.K, mesh.Np, mesh.Nfp
+    uM = u[:, :, mesh.re.Fmask]                       # (6, K, 4, Nfp)
+    flat = u.reshape(6, K * Np)
+    bnd = mesh.EToE < 0
+    idx = np.where(mesh.vmapP >= 0, mesh.vmapP, 0)
+    uP = flat[:, idx]                                  # (6, K, 4, Nfp)
+    return uM, uP, bnd
+
+
+def surface_flux(mesh, u, alpha: float = 1.0):
+    """Fscale * [n.F - (n.F)*] at every face node: (6, K, 4, Nfp)."""
+    uM, uP, bnd = traces(mesh, u)
+    dE = uM[0:3] - uP[0:3]
+    dH = uM[3:6] - uP[3:6]
+    b = bnd[None, :, :, None]
+    dE = np.where(b, 2.0 * uM[0:3], dE)
+    dH = np.where(b, 0.0, dH)
+    n = np.stack([mesh.nx, mesh.ny, mesh.nz])[:, :, :, None]  # (3, K, 4, 1)
+    ndE = np.sum(n * dE, axis=0)
+    ndH = np.sum(n * dH, axis=0)
+    fE = 0.5 * (-np.cross(n, dH, axis=0) + alpha * (n * ndE - dE))
+    fH = 0.5 * (np.cross(n, dE, axis=0) + alpha * (n * ndH - dH))
+    f = np.concatenate([fE, fH], axis=0)
+    return f * mesh.Fscale[None, :, :, None]
+
+
+def rhs(mesh, u, alpha: float = 1.0):
+    """du/dt for u of shape (6, K, Np)."""
+    u = np.asarray(u, dtype=np.float64)
+    K, Np, Nfp = mesh.K, mesh.Np, mesh.Nfp
+    out = np.empty_like(u)
+    cx, cy, cz = curl(mesh, u[3], u[4], u[5])
+    out[0], out[1], out[2] = cx, cy, cz
+    cx, cy, cz = curl(mesh, u[0], u[1], u[2])
+    out[3], out[4], out[5] = -cx, -cy, -cz
+    f = surface_flux(mesh, u, alpha).reshape(6, K, 4 * Nfp)
+    out += f @ mesh.re.LIFT.T
+    return out
