@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput of the DG Maxwell hot path on one MI355X.
+
+Workload (default): the 24^3 x 6 jittered Kuhn cube (K = 82,944 tetrahedra),
+order N = 4 (Np = 35), perfectly conducting walls, upwind flux, fields = the
+(1,1,0) cavity mode plus seeded N(0, 1e-3) noise.  One "step" is one LSERK
+time step: five right-hand-side evaluations and five stage updates over the
+whole mesh (dg_rk_step with nsteps = 1).
+
+Metric: GDOF/s per RHS evaluation = 5 * 6 * K * Np * steps / time / 1e9,
+inputs resident in HBM, timed with HIP events on the stream the library
+launches on.  The "roofline" object describes the dominant kernel (the fused
+right-hand side) from its algorithmic flop count and its average launch time
+measured here; "cpu_baseline" times the FP64 CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import dg_inputs as I  # noqa: E402
+
+PEAKS = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp64_TFs": 78.6,
+    "fp32_TFs": 157.3,
+}
+
+
+def flops_per_element(N: int) -> int:
+    """Algorithmic flops of one RHS per element: 18 Np x Np matvecs (Dr, Ds,
+    Dt of six fields), 6 Np x 4Nfp matvecs (LIFT), the upwind flux (~60 per
+    face node) and metric + curl (~66 per node)."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    return 36 * Np * Np + 48 * Np * Nfp + 240 * Nfp + 66 * Np
+
+
+def bytes_per_element(N: int, s: int) -> int:
+    """Algorithmic HBM bytes of one RHS per element: read u, write rhs
+    (6 Np scalars each), 25 geometry scalars, 16 bytes of connectivity."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    return 2 * 6 * Np * s + 25 * s + 16
+
+
+def make_problem(dg, k, N, precision):
+    VX, EToV = I.kuhn_cube(k, 0.1, 0)
+    p = dg.Problem(N, VX, EToV, precision)
+    xyz = p.nodes()
+    u = I.cavity_mode(xyz[..., 0], xyz[..., 1], xyz[..., 2]) + I.field_noise((6, p.info.K, p.info.Np), 1e-3, 1)
+    return p, u, (VX, EToV)
+
+
+def time_rhs(torch, p, du, out, reps):
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        p.rhs(du, out, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        p.rhs(du, out, stream)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(VX, EToV, N, budget_s=20.0):
+    """FP64 oracle RHS evaluations of the same workload on the host cores; the
+    oracle receives the same fields, evaluated at its own nodes."""
+    from threadpoolctl import threadpool_info
+    from oracle import maxwell as Mx
+    from oracle import mesh as Me
+    m = Me.Mesh(N, VX, EToV)
+    u = I.cavity_mode(m.x, m.y, m.z) + I.field_noise((6, m.K, m.Np), 1e-3, 1)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        Mx.rhs(m, u)
+        n += 1
+        if time.perf_counter() - t0 > budget_s / 2 or n >= 5:
+            break
+    t = (time.perf_counter() - t0) / n
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": 6 * m.K * m.Np / t / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} FP64 oracle RHS evaluations of the same K={m.K}, N={N} mesh and fields "
+                      f"(mean {t:.2f} s each); host has {os.cpu_count()} logical CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--k", type=int, default=24, help="cube resolution (K = 6 k^3)")
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--rhs-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the multi-GPU path is not part of this build "
+              "(see the design notes on how the element partition would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1211_0582_amd import dg
+
+    torch.cuda.set_device(0)
+    N, k = args.order, args.k
+    results = {}
+    for prec in (args.precision, "fp32" if args.precision == "fp64" else "fp64"):
+        p, u, mesh = make_problem(dg, k, N, prec)
+        K, Np = p.info.K, p.info.Np
+        s = p.info.elem_bytes
+        du = p.pack(u)
+        res = p.zeros_state()
+        out = p.zeros_state()
+        dt = 0.5 * p.info.dt_cfl1
+        stream = torch.cuda.current_stream()
+        t_rhs = time_rhs(torch, p, du, out, args.rhs_reps)
+        p.rk_step(du, res, 0.0, dt, args.warmup, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            p.rk_step(du, res, 0.0, dt, 1, stream)
+        e1.record(stream)
+        e1.synchronize()
+        torch.cuda.synchronize()
+        t_total = e0.elapsed_time(e1) / 1e3
+        dofs = 6 * K * Np
+        flops = flops_per_element(N) * K
+        peak = PEAKS["fp64_TFs"] if prec == "fp64" else PEAKS["fp32_TFs"]
+        achieved = flops / t_rhs / 1e12
+        results[prec] = {
+            "value": 5 * dofs * args.steps / t_total / 1e9,
+            "ms_per_step": 1e3 * t_total / args.steps,
+            "rhs_us": 1e6 * t_rhs,
+            "rhs_gdofs": dofs / t_rhs / 1e9,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak, "traffic": None,
+                         "kernel": f"rhs_valu_kernel<{N},{'double' if prec == 'fp64' else 'float'}>",
+                         "algorithmic_flops_per_launch": flops,
+                         "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K,
+                         "hbm_GBs_algorithmic": bytes_per_element(N, s) * K / t_rhs / 1e9},
+            "K": K, "Np": Np,
+        }
+        p.close()
+        del du, res, out
+
+    main_r = results[args.precision]
+    other = "fp32" if args.precision == "fp64" else "fp64"
+    line = {
+        "metric": "GDOF/s per DG RHS eval (Maxwell tets) and % of HBM/MFMA roofline",
+        "value": main_r["value"],
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"jittered Kuhn cube {k}^3x6 tets (K={main_r['K']}), N={N} (Np={main_r['Np']}), "
+                               f"PEC cavity + noise, upwind, LSERK(5,4) step = 5 RHS + 5 updates",
+                   "K": main_r["K"], "N": N, "precision": args.precision},
+        "roofline": main_r["roofline"],
+        "rhs_us": main_r["rhs_us"],
+        "rhs_gdofs": main_r["rhs_gdofs"],
+        "other_precision": {other: {kk: results[other][kk] for kk in ("value", "ms_per_step", "rhs_us", "rhs_gdofs", "roofline")}},
+    }
+    if not args.no_cpu_baseline:
+        VX, EToV = I.kuhn_cube(k, 0.1, 0)
+        line["cpu_baseline"] = cpu_baseline(VX, EToV, N)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

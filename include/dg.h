@@ -1,0 +1,147 @@
+/*
+ * dg.h -- C ABI of the MI355X (gfx950) nodal discontinuous Galerkin library
+ * for the 3D Maxwell equations on straight-sided tetrahedra.
+ *
+ * What is computed.  The semi-discrete scheme of Kloeckner, Warburton and
+ * Hesthaven, "High-Order Discontinuous Galerkin Methods by GPU
+ * Metaprogramming", Section 2 ("The Discontinuous Galerkin Method", strong
+ * form and the semi-discrete equation), for the linear Maxwell flux with
+ * eps = mu = 1 and field order u = (Ex, Ey, Ez, Hx, Hy, Hz):
+ *
+ *     du/dt = -sum_nu D^nu F(u) + L [ n.F - (n.F)* ],
+ *
+ * i.e. dE/dt = curl H + LIFT(Fscale fE), dH/dt = -curl E + LIFT(Fscale fH)
+ * with the upwind flux of the paper's results section (Maxwell flux figure,
+ * part a; H part by duality), dE = E- - E+, dH = H- - H+:
+ *     fE = 1/2 [ -n x dH + alpha (n (n.dE) - dE) ]
+ *     fH = 1/2 [  n x dE + alpha (n (n.dH) - dH) ],
+ * perfectly conducting walls (E+ = -E-, H+ = H-) on every unmatched face, and
+ * the five-stage fourth-order low-storage Runge-Kutta scheme of Carpenter and
+ * Kennedy for time stepping ("including RK4 timestepping", Section 6).
+ *
+ * Reference element: nodal Lagrange basis of P_N on warp & blend nodes,
+ * operators built from an orthonormal basis; reference tetrahedron
+ * v0=(-1,-1,-1), v1=(1,-1,-1), v2=(-1,1,-1), v3=(-1,-1,1); element map
+ * x = -(1+r+s+t)/2 X0 + (1+r)/2 X1 + (1+s)/2 X2 + (1+t)/2 X3 with X_i the
+ * vertices EToV[k][i].  Node order: t lattice index outermost, then s, then r.
+ *
+ * Conventions for every call:
+ *   - every function returns dg_status (0 = DG_OK, negative = error); nothing
+ *     throws across the ABI; dg_last_error() gives a thread-local message;
+ *   - invalid arguments are rejected before any device work is queued;
+ *   - "device pointer" arguments are HIP device allocations owned by the
+ *     caller, "host pointer" arguments are ordinary host memory;
+ *   - stream arguments are hipStream_t values passed as void* (NULL = the
+ *     null stream); calls that take a stream are asynchronous on it and
+ *     neither allocate nor synchronise;
+ *   - the device that was current at dg_setup_mesh must be current when a
+ *     problem's device calls are made.
+ */
+#ifndef DG_H_
+#define DG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,        /* bad argument (null pointer, size, enum value)        */
+  DG_EMESH = -2,         /* invalid mesh: J <= 0, bad vertex index, a face shared
+                            by more than two elements; the message names it    */
+  DG_EHIP = -3,          /* a HIP runtime call failed; the message has its text  */
+  DG_ENOMEM = -4,        /* device or host allocation failed                     */
+  DG_EUNSUPPORTED = -5   /* valid request this build does not support (order,
+                            precision, size limits)                             */
+} dg_status;
+
+/* Arithmetic of the right-hand side and of the state arrays.
+ *   DG_FP64: state, geometry, operators and all arithmetic in binary64.
+ *   DG_FP32: state, geometry, operators and all arithmetic in binary32.     */
+typedef enum { DG_FP64 = 0, DG_FP32 = 1 } dg_precision;
+
+typedef struct dg_problem_s* dg_problem;  /* opaque; owns all mesh-derived device data */
+
+/* Mesh and discretisation (inputs of dg_setup_mesh).  Host pointers; the
+ * library copies what it needs, the caller keeps ownership. */
+typedef struct {
+  int32_t N;             /* polynomial order, 1..9                                */
+  int32_t precision;     /* dg_precision                                          */
+  double alpha;          /* flux parameter: 1 = upwind, 0 = central; finite      */
+  int64_t Nv;            /* number of vertices                                    */
+  const double* VX;      /* host, Nv x 3 row-major (x, y, z)                      */
+  int64_t K;             /* number of tetrahedra, 1 .. 2^26-1                     */
+  const int32_t* EToV;   /* host, K x 4 row-major, 0-based vertex ids; every
+                            element must be positively oriented (J > 0)          */
+} dg_mesh_desc;
+
+/* Layout of device state arrays (u, rhs, res).  A state array holds the six
+ * fields one after the other, field c starting at element offset
+ * c * field_stride; inside a field, element k's Np nodal values are
+ * contiguous at offset k * Np.  Entries between K*Np and field_stride are
+ * padding: never read as data.  state_elems = 6 * field_stride scalars of
+ * elem_bytes bytes each. */
+typedef struct {
+  int32_t N, Np, Nfp, precision;
+  int64_t K;
+  int64_t field_stride;  /* scalars                                               */
+  int64_t state_elems;   /* scalars in one state array                            */
+  int32_t elem_bytes;    /* 8 (FP64) or 4 (FP32)                                  */
+  int32_t tile_elems;    /* elements per workgroup of the RHS kernel              */
+  double dt_cfl1;        /* 2 / ((N+1)^2 max Fscale): dt at CFL number 1          */
+  double alpha;
+  int64_t n_boundary_faces;
+} dg_info;
+
+/* Builds the reference element, geometry, connectivity and uploads them to
+ * the current HIP device.  Synchronous.  *out receives a new handle on
+ * success and is left untouched on error.
+ * Errors: DG_EINVAL (null pointer, K or Nv < 1, alpha not finite, precision
+ * out of range), DG_EUNSUPPORTED (N outside 1..9, K too large), DG_EMESH
+ * (vertex id out of range, J <= 0, face multiplicity > 2), DG_EHIP/DG_ENOMEM. */
+dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out);
+
+/* Sizes and layout of a problem.  Errors: DG_EINVAL on null arguments. */
+dg_status dg_info_get(dg_problem p, dg_info* info);
+
+/* rhs <- du/dt evaluated at u (semi-discrete scheme, Section 2; flux as in
+ * the header comment).  u, rhs: device pointers to state arrays in the
+ * problem's precision and layout; they must not overlap.  Asynchronous on
+ * stream.  Only the K*Np entries of each field of rhs are written.
+ * Errors: DG_EINVAL (null pointer or u == rhs), DG_EHIP (launch failure). */
+dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
+
+/* nsteps steps of the 5-stage low-storage RK4 scheme, in place:
+ *   for each stage s: res <- A_s res + dt du/dt(u);  u <- u + B_s res,
+ * A_1 = 0, so res needs no initial value.  u, res: device state arrays.
+ * t is the start time; the perfectly conducting cavity has no time-dependent
+ * data, so the stage times t + C_s dt do not enter the arithmetic.
+ * Uses library-owned scratch allocated at setup; asynchronous on stream.
+ * Errors: DG_EINVAL (null pointer, u == res, nsteps < 0, dt not finite). */
+dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
+                     int32_t nsteps, void* stream);
+
+/* Host <-> device conversion between the canonical host layout
+ * [6][K][Np] binary64 (host pointer) and a device state array (layout above,
+ * problem precision).  dg_pack zeroes the padding.  Both block until the copy
+ * has finished on stream.  Errors: DG_EINVAL, DG_EHIP, DG_ENOMEM. */
+dg_status dg_pack(dg_problem p, const double* host_u, void* dev_u, void* stream);
+dg_status dg_unpack(dg_problem p, const void* dev_u, double* host_u, void* stream);
+
+/* Physical node coordinates, host pointer K x Np x 3 (x, y, z) binary64. */
+dg_status dg_nodes(dg_problem p, double* host_xyz);
+
+/* Releases every device and host resource of p; NULL is a no-op.  The caller
+ * must ensure no queued work still uses p. */
+void dg_destroy(dg_problem p);
+
+/* Thread-local text of the last error ("" if none). */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H_ */

@@ -1,0 +1,341 @@
+// C ABI of the DG library: setup, right-hand side, LSERK stepping, layout
+// conversion.  Host setup (reference element, geometry, connectivity) is in
+// host_refelem.cpp / host_mesh.cpp; the kernels are in rhs_valu.hpp and
+// lserk.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+#include "dg_host.h"
+#include "device_common.hpp"
+#include "host_common.hpp"
+
+using namespace dgh;
+
+struct dg_problem_s {
+  int N = 0, Np = 0, Nfp = 0, precision = 0, elem_bytes = 8, tile = 1, device = 0;
+  int64_t K = 0, fs = 0, state_elems = 0, n_boundary = 0;
+  double alpha = 1.0, dt_cfl1 = 0.0;
+  void* d_geo = nullptr;
+  int32_t* d_conn = nullptr;
+  void* d_ops = nullptr;
+  uint8_t* d_nbr = nullptr;
+  int32_t* d_fmask = nullptr;
+  void* d_scratch = nullptr;  // rhs buffer of dg_rk_step
+  std::vector<double> verts;  // K x 4 x 3 vertex coordinates (for dg_nodes)
+  dgd::RhsLauncher rhs = nullptr;
+};
+
+namespace {
+
+// Coefficients of the five-stage, fourth-order 2N-storage Runge-Kutta scheme
+// of Carpenter and Kennedy (1994).
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+dg_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define DG_HIP(call, what)                       \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+void free_problem(dg_problem p) {
+  if (!p) return;
+  hipFree(p->d_geo);
+  hipFree(p->d_conn);
+  hipFree(p->d_ops);
+  hipFree(p->d_nbr);
+  hipFree(p->d_fmask);
+  hipFree(p->d_scratch);
+  delete p;
+}
+
+template <typename T>
+dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
+  const int Np = re.Np, NF = 4 * re.Nfp;
+  const int64_t K = hm.K;
+  // Geometry records.
+  std::vector<T> geo(size_t(K) * dgd::kGeoStride);
+  for (int64_t k = 0; k < K; ++k) {
+    T* g = &geo[size_t(k) * dgd::kGeoStride];
+    for (int i = 0; i < 9; ++i) g[i] = T(hm.metric[size_t(k) * 9 + i]);
+    for (int i = 0; i < 16; ++i) g[9 + i] = T(hm.face[size_t(k) * 16 + i]);
+  }
+  // Operators, transposed so that lanes holding consecutive output rows read
+  // consecutive addresses.
+  std::vector<T> ops(size_t(3) * Np * Np + size_t(NF) * Np);
+  const Mat* D[3] = {&re.Dr, &re.Ds, &re.Dt};
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < Np; ++i)
+      for (int j = 0; j < Np; ++j) ops[size_t(d) * Np * Np + size_t(j) * Np + i] = T((*D[d])(i, j));
+  for (int i = 0; i < Np; ++i)
+    for (int m = 0; m < NF; ++m) ops[size_t(3) * Np * Np + size_t(m) * Np + i] = T(re.LIFT(i, m));
+
+  DG_HIP(hipMalloc(&p->d_geo, geo.size() * sizeof(T)), "hipMalloc(geometry)");
+  DG_HIP(hipMalloc(&p->d_conn, hm.conn.size() * sizeof(int32_t)), "hipMalloc(connectivity)");
+  DG_HIP(hipMalloc(&p->d_ops, ops.size() * sizeof(T)), "hipMalloc(operators)");
+  DG_HIP(hipMalloc(&p->d_nbr, re.nbr_node.size()), "hipMalloc(neighbour table)");
+  DG_HIP(hipMalloc(&p->d_fmask, re.fmask.size() * sizeof(int32_t)), "hipMalloc(fmask)");
+  DG_HIP(hipMalloc(&p->d_scratch, size_t(p->state_elems) * sizeof(T)), "hipMalloc(scratch)");
+  DG_HIP(hipMemcpy(p->d_geo, geo.data(), geo.size() * sizeof(T), hipMemcpyHostToDevice), "upload geometry");
+  DG_HIP(hipMemcpy(p->d_conn, hm.conn.data(), hm.conn.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+         "upload connectivity");
+  DG_HIP(hipMemcpy(p->d_ops, ops.data(), ops.size() * sizeof(T), hipMemcpyHostToDevice), "upload operators");
+  DG_HIP(hipMemcpy(p->d_nbr, re.nbr_node.data(), re.nbr_node.size(), hipMemcpyHostToDevice), "upload table");
+  std::vector<int32_t> fm(re.fmask.begin(), re.fmask.end());
+  DG_HIP(hipMemcpy(p->d_fmask, fm.data(), fm.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload fmask");
+  DG_HIP(hipMemset(p->d_scratch, 0, size_t(p->state_elems) * sizeof(T)), "clear scratch");
+  return DG_OK;
+}
+
+dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
+  dgd::RhsArgs a;
+  a.u = u;
+  a.rhs = rhs;
+  a.geo = p->d_geo;
+  a.conn = p->d_conn;
+  a.ops = p->d_ops;
+  a.nbr = p->d_nbr;
+  a.fmask = p->d_fmask;
+  a.K = p->K;
+  a.fs = p->fs;
+  a.alpha = p->alpha;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return error_text(); }
+
+dg_status dg_host_ref_nodes(int32_t N, double* r, double* s, double* t) {
+  clear_error();
+  if (!r || !s || !t) return fail(DG_EINVAL, "null output");
+  const RefElement* re = ref_element(N);
+  if (!re) return fail(DG_EUNSUPPORTED, "order N must be in 1..9");
+  std::memcpy(r, re->r.data(), sizeof(double) * re->Np);
+  std::memcpy(s, re->s.data(), sizeof(double) * re->Np);
+  std::memcpy(t, re->t.data(), sizeof(double) * re->Np);
+  return DG_OK;
+}
+
+dg_status dg_host_ref_operators(int32_t N, double* Dr, double* Ds, double* Dt, double* LIFT, int32_t* Fmask,
+                                double* Mf) {
+  clear_error();
+  const RefElement* re = ref_element(N);
+  if (!re) return fail(DG_EUNSUPPORTED, "order N must be in 1..9");
+  const size_t nn = size_t(re->Np) * re->Np;
+  if (Dr) std::memcpy(Dr, re->Dr.a.data(), nn * sizeof(double));
+  if (Ds) std::memcpy(Ds, re->Ds.a.data(), nn * sizeof(double));
+  if (Dt) std::memcpy(Dt, re->Dt.a.data(), nn * sizeof(double));
+  if (LIFT) std::memcpy(LIFT, re->LIFT.a.data(), re->LIFT.a.size() * sizeof(double));
+  if (Fmask)
+    for (size_t i = 0; i < re->fmask.size(); ++i) Fmask[i] = re->fmask[i];
+  if (Mf) std::memcpy(Mf, re->Mf.data(), re->Mf.size() * sizeof(double));
+  return DG_OK;
+}
+
+dg_status dg_host_mesh(int32_t N, int64_t Nv, const double* VX, int64_t K, const int32_t* EToV, double* metric,
+                       double* J, double* face, double* sJ, int64_t* vmapP, int32_t* conn) {
+  clear_error();
+  HostMesh hm;
+  dg_status st = build_mesh(N, Nv, VX, K, EToV, hm);
+  if (st != DG_OK) return st;
+  const RefElement* re = ref_element(N);
+  if (!re) return fail(DG_EUNSUPPORTED, "reference element construction failed");
+  if (metric) std::memcpy(metric, hm.metric.data(), hm.metric.size() * sizeof(double));
+  if (J) std::memcpy(J, hm.J.data(), hm.J.size() * sizeof(double));
+  if (face) std::memcpy(face, hm.face.data(), hm.face.size() * sizeof(double));
+  if (sJ) std::memcpy(sJ, hm.sJ.data(), hm.sJ.size() * sizeof(double));
+  if (conn) std::memcpy(conn, hm.conn.data(), hm.conn.size() * sizeof(int32_t));
+  if (vmapP) {
+    const int Np = re->Np, Nfp = re->Nfp;
+    for (int64_t k = 0; k < K; ++k)
+      for (int f = 0; f < 4; ++f) {
+        const int32_t c = hm.conn[size_t(k) * 4 + f];
+        for (int j = 0; j < Nfp; ++j) {
+          int64_t v = -1;
+          if (c >= 0) v = int64_t(c >> 5) * Np + re->nbr_node[(f * 24 + (c & 31)) * Nfp + j];
+          vmapP[(size_t(k) * 4 + f) * Nfp + j] = v;
+        }
+      }
+  }
+  return DG_OK;
+}
+
+dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
+  clear_error();
+  if (!desc || !out) return fail(DG_EINVAL, "null argument");
+  if (desc->precision != DG_FP64 && desc->precision != DG_FP32)
+    return fail(DG_EINVAL, "precision must be DG_FP64 or DG_FP32");
+  if (!std::isfinite(desc->alpha)) return fail(DG_EINVAL, "alpha must be finite");
+  if (desc->N < 1 || desc->N > kMaxOrder) return fail(DG_EUNSUPPORTED, "order N must be in 1..9");
+  HostMesh hm;
+  dg_status st = build_mesh(desc->N, desc->Nv, desc->VX, desc->K, desc->EToV, hm);
+  if (st != DG_OK) return st;
+  const RefElement* re = ref_element(desc->N);
+  if (!re) return fail(DG_EUNSUPPORTED, "reference element construction failed");
+
+  auto p = new dg_problem_s();
+  p->N = desc->N;
+  p->Np = re->Np;
+  p->Nfp = re->Nfp;
+  p->precision = desc->precision;
+  p->elem_bytes = desc->precision == DG_FP64 ? 8 : 4;
+  p->K = desc->K;
+  p->alpha = desc->alpha;
+  // Each field starts on a 256-byte boundary.
+  const int64_t align = 256 / p->elem_bytes;
+  p->fs = ((p->K * p->Np + align - 1) / align) * align;
+  p->state_elems = 6 * p->fs;
+  p->n_boundary = hm.n_boundary;
+  p->dt_cfl1 = 2.0 / ((desc->N + 1.0) * (desc->N + 1.0) * hm.max_fscale);
+  p->tile = dgd::rhs_tile(desc->N, desc->precision);
+  p->rhs = dgd::rhs_launcher(desc->N, desc->precision);
+  hipGetDevice(&p->device);
+  p->verts.resize(size_t(p->K) * 12);
+  for (int64_t k = 0; k < p->K; ++k)
+    for (int v = 0; v < 4; ++v)
+      for (int d = 0; d < 3; ++d) p->verts[size_t(k) * 12 + v * 3 + d] = desc->VX[3 * int64_t(desc->EToV[4 * k + v]) + d];
+  st = (p->precision == DG_FP64) ? upload<double>(p, *re, hm) : upload<float>(p, *re, hm);
+  if (st != DG_OK) {
+    free_problem(p);
+    return st;
+  }
+  *out = p;
+  return DG_OK;
+}
+
+dg_status dg_info_get(dg_problem p, dg_info* info) {
+  clear_error();
+  if (!p || !info) return fail(DG_EINVAL, "null argument");
+  info->N = p->N;
+  info->Np = p->Np;
+  info->Nfp = p->Nfp;
+  info->precision = p->precision;
+  info->K = p->K;
+  info->field_stride = p->fs;
+  info->state_elems = p->state_elems;
+  info->elem_bytes = p->elem_bytes;
+  info->tile_elems = p->tile;
+  info->dt_cfl1 = p->dt_cfl1;
+  info->alpha = p->alpha;
+  info->n_boundary_faces = p->n_boundary;
+  return DG_OK;
+}
+
+dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream) {
+  clear_error();
+  if (!p || !u || !rhs) return fail(DG_EINVAL, "null argument");
+  if (u == rhs) return fail(DG_EINVAL, "u and rhs must not alias");
+  if (!p->rhs) return fail(DG_EUNSUPPORTED, "no kernel for this order/precision");
+  hipError_t e = p->rhs(rhs_args(p, u, rhs), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
+  return DG_OK;
+}
+
+dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int32_t nsteps, void* stream) {
+  clear_error();
+  (void)t;
+  if (!p || !u || !res) return fail(DG_EINVAL, "null argument");
+  if (u == res) return fail(DG_EINVAL, "u and res must not alias");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dgd::RhsArgs ra = rhs_args(p, u, p->d_scratch);
+  for (int32_t n = 0; n < nsteps; ++n)
+    for (int st = 0; st < 5; ++st) {
+      hipError_t e = p->rhs(ra, s);
+      if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
+      dgd::UpdateArgs ua;
+      ua.u = u;
+      ua.res = res;
+      ua.rhs = p->d_scratch;
+      ua.n = p->K * p->Np;
+      ua.fs = p->fs;
+      ua.a = kRkA[st];
+      ua.b = kRkB[st];
+      ua.dt = dt;
+      e = dgd::launch_update(ua, p->precision, s);
+      if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+    }
+  return DG_OK;
+}
+
+dg_status dg_pack(dg_problem p, const double* host_u, void* dev_u, void* stream) {
+  clear_error();
+  if (!p || !host_u || !dev_u) return fail(DG_EINVAL, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = p->K * p->Np;
+  if (p->precision == DG_FP64) {
+    std::vector<double> st(size_t(p->state_elems), 0.0);
+    for (int c = 0; c < 6; ++c) std::memcpy(&st[size_t(c * p->fs)], host_u + c * n, size_t(n) * sizeof(double));
+    DG_HIP(hipMemcpyAsync(dev_u, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s), "pack copy");
+    DG_HIP(hipStreamSynchronize(s), "pack sync");
+  } else {
+    std::vector<float> st(size_t(p->state_elems), 0.0f);
+    for (int c = 0; c < 6; ++c)
+      for (int64_t i = 0; i < n; ++i) st[size_t(c * p->fs + i)] = float(host_u[c * n + i]);
+    DG_HIP(hipMemcpyAsync(dev_u, st.data(), st.size() * sizeof(float), hipMemcpyHostToDevice, s), "pack copy");
+    DG_HIP(hipStreamSynchronize(s), "pack sync");
+  }
+  return DG_OK;
+}
+
+dg_status dg_unpack(dg_problem p, const void* dev_u, double* host_u, void* stream) {
+  clear_error();
+  if (!p || !host_u || !dev_u) return fail(DG_EINVAL, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = p->K * p->Np;
+  if (p->precision == DG_FP64) {
+    std::vector<double> st(size_t(p->state_elems));
+    DG_HIP(hipMemcpyAsync(st.data(), dev_u, st.size() * sizeof(double), hipMemcpyDeviceToHost, s), "unpack copy");
+    DG_HIP(hipStreamSynchronize(s), "unpack sync");
+    for (int c = 0; c < 6; ++c) std::memcpy(host_u + c * n, &st[size_t(c * p->fs)], size_t(n) * sizeof(double));
+  } else {
+    std::vector<float> st(size_t(p->state_elems));
+    DG_HIP(hipMemcpyAsync(st.data(), dev_u, st.size() * sizeof(float), hipMemcpyDeviceToHost, s), "unpack copy");
+    DG_HIP(hipStreamSynchronize(s), "unpack sync");
+    for (int c = 0; c < 6; ++c)
+      for (int64_t i = 0; i < n; ++i) host_u[c * n + i] = double(st[size_t(c * p->fs + i)]);
+  }
+  return DG_OK;
+}
+
+dg_status dg_nodes(dg_problem p, double* host_xyz) {
+  clear_error();
+  if (!p || !host_xyz) return fail(DG_EINVAL, "null argument");
+  const RefElement* re = ref_element(p->N);
+  for (int64_t k = 0; k < p->K; ++k) {
+    const double* X = &p->verts[size_t(k) * 12];
+    for (int i = 0; i < p->Np; ++i) {
+      const double l0 = -0.5 * (1.0 + re->r[i] + re->s[i] + re->t[i]);
+      const double l1 = 0.5 * (1.0 + re->r[i]), l2 = 0.5 * (1.0 + re->s[i]), l3 = 0.5 * (1.0 + re->t[i]);
+      for (int d = 0; d < 3; ++d)
+        host_xyz[(size_t(k) * p->Np + i) * 3 + d] = l0 * X[d] + l1 * X[3 + d] + l2 * X[6 + d] + l3 * X[9 + d];
+    }
+  }
+  return DG_OK;
+}
+
+void dg_destroy(dg_problem p) { free_problem(p); }
+
+}  // extern "C"

@@ -1,0 +1,48 @@
+// Device-side declarations shared by the kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgd {
+
+// Per-element geometry record on the device: 25 scalars,
+//   [0..8]   rx ry rz sx sy sz tx ty tz
+//   [9+4f .. 12+4f] face f: nx ny nz Fscale
+constexpr int kGeoStride = 25;
+
+// Arguments of one right-hand-side evaluation.
+struct RhsArgs {
+  const void* u;          // state, [6][field_stride], element-major inside a field
+  void* rhs;              // output, same layout
+  const void* geo;        // K x kGeoStride
+  const int32_t* conn;    // K x 4, -1 wall, else nbr*32 + nbr_face*6 + orient
+  const void* ops;        // Dr^T, Ds^T, Dt^T (Np x Np each, [j][i]), LIFT^T (4Nfp x Np, [m][i])
+  const uint8_t* nbr;     // 4 x 24 x Nfp neighbour volume node per (face, code, j)
+  const int32_t* fmask;   // 4 x Nfp
+  int64_t K;
+  int64_t fs;             // field stride in scalars
+  double alpha;
+};
+
+// Arguments of one LSERK stage update: res <- a res + dt rhs; u <- u + b res.
+struct UpdateArgs {
+  void* u;
+  void* res;
+  const void* rhs;
+  int64_t n;              // K * Np scalars per field
+  int64_t fs;
+  double a, b, dt;
+};
+
+using RhsLauncher = hipError_t (*)(const RhsArgs&, hipStream_t);
+
+// Launcher table: order N (1..9), precision 0 = FP64, 1 = FP32.
+RhsLauncher rhs_launcher(int N, int precision);
+// Elements per workgroup of the RHS kernel.
+int rhs_tile(int N, int precision);
+
+hipError_t launch_update(const UpdateArgs& a, int precision, hipStream_t s);
+
+}  // namespace dgd

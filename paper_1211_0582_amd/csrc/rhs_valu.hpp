@@ -1,0 +1,171 @@
+// Fused DG Maxwell right-hand side, vector-ALU variant (FP64 / FP32).
+//
+// One workgroup of 256 lanes owns a tile of E consecutive elements and does
+// all four stages of the operator split of Section 2.1 for them:
+//   1. the tile's nodal fields are copied from HBM to LDS (coalesced: each
+//      field holds the tile's E*Np values contiguously);
+//   2. flux gather: one lane per (element, face node) reads the own trace
+//      from LDS and the neighbour trace from global memory through the
+//      neighbour-node table, evaluates the upwind flux, scales it by Fscale
+//      and stores it in LDS (the facial buffer of Section 3 never goes to HBM);
+//   3. local differentiation + lifting: one lane per (element, node) forms
+//      Dr, Ds, Dt of all six fields from the LDS tile (operator columns read
+//      coalesced from the transposed matrices), applies the element's
+//      constant metric to get curl H and -curl E, adds LIFT (Fscale f) and
+//      writes the result.
+// The orders N, Np, Nfp and the tile E are compile-time constants, so every
+// loop has a fixed trip count (the paper's "hard-coded sizes").
+#pragma once
+
+#include "device_common.hpp"
+
+namespace dgd {
+
+template <int N>
+struct Order {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int NF = 4 * Nfp;
+};
+
+// Elements per workgroup: about two passes of 256 lanes over (element, node),
+// capped so the LDS tile stays under 64 KiB in FP64.
+template <int N>
+constexpr int valu_tile() {
+  constexpr int Np = Order<N>::Np, NF = Order<N>::NF;
+  int e = 512 / Np;
+  if (e > 64) e = 64;
+  const int cap = 65536 / (48 * (Np + NF));
+  if (e > cap) e = cap;
+  return e < 1 ? 1 : e;
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(256) void rhs_valu_kernel(RhsArgs a) {
+  constexpr int Np = Order<N>::Np, Nfp = Order<N>::Nfp, NF = Order<N>::NF;
+  constexpr int E = valu_tile<N>();
+  __shared__ T su[6][E * Np];
+  __shared__ T sf[6][E * NF];
+
+  const T* __restrict__ u = static_cast<const T*>(a.u);
+  T* __restrict__ rhs = static_cast<T*>(a.rhs);
+  const T* __restrict__ geo = static_cast<const T*>(a.geo);
+  const T* __restrict__ ops = static_cast<const T*>(a.ops);
+  const T* __restrict__ DrT = ops;
+  const T* __restrict__ DsT = ops + Np * Np;
+  const T* __restrict__ DtT = ops + 2 * Np * Np;
+  const T* __restrict__ LiftT = ops + 3 * Np * Np;
+  const int64_t fs = a.fs;
+  const int64_t k0 = int64_t(blockIdx.x) * E;
+  const int ne = int((a.K - k0) < E ? (a.K - k0) : E);
+  const int tid = threadIdx.x;
+
+  // 1. tile -> LDS
+  for (int c = 0; c < 6; ++c) {
+    const T* src = u + c * fs + k0 * Np;
+    for (int i = tid; i < ne * Np; i += 256) su[c][i] = src[i];
+  }
+  __syncthreads();
+
+  // 2. flux gather
+  const T alpha = T(a.alpha);
+  for (int w = tid; w < ne * NF; w += 256) {
+    const int e = w / NF;
+    const int m = w - e * NF;
+    const int f = m / Nfp;
+    const int j = m - f * Nfp;
+    const int64_t k = k0 + e;
+    const int own = e * Np + a.fmask[m];
+    const T ex = su[0][own], ey = su[1][own], ez = su[2][own];
+    const T hx = su[3][own], hy = su[4][own], hz = su[5][own];
+    T dex, dey, dez, dhx, dhy, dhz;
+    const int32_t code = a.conn[k * 4 + f];
+    if (code >= 0) {
+      const int64_t nk = code >> 5;
+      const int nn = a.nbr[(f * 24 + (code & 31)) * Nfp + j];
+      const int64_t g = nk * Np + nn;
+      dex = ex - u[g];
+      dey = ey - u[fs + g];
+      dez = ez - u[2 * fs + g];
+      dhx = hx - u[3 * fs + g];
+      dhy = hy - u[4 * fs + g];
+      dhz = hz - u[5 * fs + g];
+    } else {  // perfectly conducting wall: E+ = -E-, H+ = H-
+      dex = T(2) * ex;
+      dey = T(2) * ey;
+      dez = T(2) * ez;
+      dhx = dhy = dhz = T(0);
+    }
+    const T* gf = geo + k * kGeoStride + 9 + 4 * f;
+    const T nx = gf[0], ny = gf[1], nz = gf[2];
+    const T sc = T(0.5) * gf[3];
+    const T ndE = nx * dex + ny * dey + nz * dez;
+    const T ndH = nx * dhx + ny * dhy + nz * dhz;
+    // fE = 1/2 [ -n x dH + alpha (n (n.dE) - dE) ]
+    sf[0][w] = sc * (-(ny * dhz - nz * dhy) + alpha * (nx * ndE - dex));
+    sf[1][w] = sc * (-(nz * dhx - nx * dhz) + alpha * (ny * ndE - dey));
+    sf[2][w] = sc * (-(nx * dhy - ny * dhx) + alpha * (nz * ndE - dez));
+    // fH = 1/2 [ n x dE + alpha (n (n.dH) - dH) ]
+    sf[3][w] = sc * ((ny * dez - nz * dey) + alpha * (nx * ndH - dhx));
+    sf[4][w] = sc * ((nz * dex - nx * dez) + alpha * (ny * ndH - dhy));
+    sf[5][w] = sc * ((nx * dey - ny * dex) + alpha * (nz * ndH - dhz));
+  }
+  __syncthreads();
+
+  // 3. local differentiation, curl, lifting
+  for (int w = tid; w < ne * Np; w += 256) {
+    const int e = w / Np;
+    const int i = w - e * Np;
+    T d[6][3];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) d[c][0] = d[c][1] = d[c][2] = T(0);
+    const T* ue = &su[0][e * Np];
+#pragma unroll 5
+    for (int j = 0; j < Np; ++j) {
+      const T dr = DrT[j * Np + i], ds = DsT[j * Np + i], dt = DtT[j * Np + i];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const T v = ue[c * (E * Np) + j];
+        d[c][0] += dr * v;
+        d[c][1] += ds * v;
+        d[c][2] += dt * v;
+      }
+    }
+    const int64_t k = k0 + e;
+    const T* g = geo + k * kGeoStride;
+    const T rx = g[0], ry = g[1], rz = g[2], sx = g[3], sy = g[4], sz = g[5], tx = g[6], ty = g[7], tz = g[8];
+    // physical derivative of field c along x, y, z
+#define DX(c) (rx * d[c][0] + sx * d[c][1] + tx * d[c][2])
+#define DY(c) (ry * d[c][0] + sy * d[c][1] + ty * d[c][2])
+#define DZ(c) (rz * d[c][0] + sz * d[c][1] + tz * d[c][2])
+    T out[6];
+    out[0] = DY(5) - DZ(4);     // (curl H)_x
+    out[1] = DZ(3) - DX(5);     // (curl H)_y
+    out[2] = DX(4) - DY(3);     // (curl H)_z
+    out[3] = -(DY(2) - DZ(1));  // -(curl E)_x
+    out[4] = -(DZ(0) - DX(2));  // -(curl E)_y
+    out[5] = -(DX(1) - DY(0));  // -(curl E)_z
+#undef DX
+#undef DY
+#undef DZ
+    const T* fe = &sf[0][e * NF];
+#pragma unroll 4
+    for (int m = 0; m < NF; ++m) {
+      const T l = LiftT[m * Np + i];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[c] += l * fe[c * (E * NF) + m];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) rhs[c * fs + k * Np + i] = out[c];
+  }
+}
+
+template <int N, typename T>
+hipError_t launch_rhs_valu(const RhsArgs& a, hipStream_t s) {
+  constexpr int E = valu_tile<N>();
+  const unsigned grid = unsigned((a.K + E - 1) / E);
+  hipLaunchKernelGGL((rhs_valu_kernel<N, T>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace dgd

@@ -1,0 +1,254 @@
+"""Python binding of the C ABI in include/dg.h and include/dg_host.h.
+
+Argument marshalling only: every computation happens in libdg.so (host setup
+in C++, the right-hand side and time stepping in HIP kernels).  PyTorch is
+used for device memory and streams.  If the library is missing the import
+of this module fails; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+DG_OK, DG_EINVAL, DG_EMESH, DG_EHIP, DG_ENOMEM, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+DG_FP64, DG_FP32 = 0, 1
+PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32}
+
+#: every symbol the public headers declare
+EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",
+            "dg_destroy", "dg_last_error", "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
+
+
+class DgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dg status {status}: {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("precision", C.c_int32), ("alpha", C.c_double),
+                ("Nv", C.c_int64), ("VX", C.POINTER(C.c_double)),
+                ("K", C.c_int64), ("EToV", C.POINTER(C.c_int32))]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_int32), ("Np", C.c_int32), ("Nfp", C.c_int32), ("precision", C.c_int32),
+                ("K", C.c_int64), ("field_stride", C.c_int64), ("state_elems", C.c_int64),
+                ("elem_bytes", C.c_int32), ("tile_elems", C.c_int32), ("dt_cfl1", C.c_double),
+                ("alpha", C.c_double), ("n_boundary_faces", C.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1211_0582_amd.build`")
+    # PyTorch ships its own HIP runtime with the same SONAME as the system one.
+    # Loading torch first makes libdg.so bind to that runtime, so the process
+    # holds exactly one HIP runtime and device pointers/streams are shared.
+    import torch  # noqa: F401
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "dg_setup_mesh": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(P)]),
+        "dg_info_get": (C.c_int, [P, C.POINTER(Info)]),
+        "dg_rhs": (C.c_int, [P, P, P, P]),
+        "dg_rk_step": (C.c_int, [P, P, P, C.c_double, C.c_double, C.c_int32, P]),
+        "dg_pack": (C.c_int, [P, P, P, P]),
+        "dg_unpack": (C.c_int, [P, P, P, P]),
+        "dg_nodes": (C.c_int, [P, P]),
+        "dg_destroy": (None, [P]),
+        "dg_last_error": (C.c_char_p, []),
+        "dg_host_ref_nodes": (C.c_int, [C.c_int32, P, P, P]),
+        "dg_host_ref_operators": (C.c_int, [C.c_int32, P, P, P, P, P, P]),
+        "dg_host_mesh": (C.c_int, [C.c_int32, C.c_int64, P, C.c_int64, P, P, P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != DG_OK:
+        raise DgError(status, lib.dg_last_error().decode())
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def n_p(N):
+    return (N + 1) * (N + 2) * (N + 3) // 6
+
+
+def n_fp(N):
+    return (N + 1) * (N + 2) // 2
+
+
+# ---------------------------------------------------------------------------
+# Host-side calls (no GPU needed)
+# ---------------------------------------------------------------------------
+def dg_host_ref_nodes(N):
+    Np = n_p(N)
+    r, s, t = (np.zeros(Np) for _ in range(3))
+    _check(lib.dg_host_ref_nodes(N, _ptr(r), _ptr(s), _ptr(t)))
+    return r, s, t
+
+
+def dg_host_ref_operators(N):
+    Np, Nfp = n_p(N), n_fp(N)
+    Dr, Ds, Dt = (np.zeros((Np, Np)) for _ in range(3))
+    LIFT = np.zeros((Np, 4 * Nfp))
+    Fmask = np.zeros((4, Nfp), dtype=np.int32)
+    Mf = np.zeros((4, Nfp, Nfp))
+    _check(lib.dg_host_ref_operators(N, _ptr(Dr), _ptr(Ds), _ptr(Dt), _ptr(LIFT), _ptr(Fmask), _ptr(Mf)))
+    return dict(Dr=Dr, Ds=Ds, Dt=Dt, LIFT=LIFT, Fmask=Fmask, Mf=Mf)
+
+
+def dg_host_mesh(N, VX, EToV):
+    VX = np.ascontiguousarray(VX, dtype=np.float64)
+    EToV = np.ascontiguousarray(EToV, dtype=np.int32)
+    K = EToV.shape[0]
+    Nfp = n_fp(N)
+    out = dict(metric=np.zeros((K, 9)), J=np.zeros(K), face=np.zeros((K, 4, 4)), sJ=np.zeros((K, 4)),
+               vmapP=np.zeros((K, 4, Nfp), dtype=np.int64), conn=np.zeros((K, 4), dtype=np.int32))
+    _check(lib.dg_host_mesh(N, VX.shape[0], _ptr(VX), K, _ptr(EToV), _ptr(out["metric"]), _ptr(out["J"]),
+                            _ptr(out["face"]), _ptr(out["sJ"]), _ptr(out["vmapP"]), _ptr(out["conn"])))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Device calls
+# ---------------------------------------------------------------------------
+def dg_setup_mesh(N, VX, EToV, precision=DG_FP64, alpha=1.0):
+    VX = np.ascontiguousarray(VX, dtype=np.float64)
+    EToV = np.ascontiguousarray(EToV, dtype=np.int32)
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    d = MeshDesc(N, precision, alpha, VX.shape[0], VX.ctypes.data_as(C.POINTER(C.c_double)),
+                 EToV.shape[0], EToV.ctypes.data_as(C.POINTER(C.c_int32)))
+    h = C.c_void_p()
+    _check(lib.dg_setup_mesh(C.byref(d), C.byref(h)))
+    return h
+
+
+def dg_info_get(p):
+    info = Info()
+    _check(lib.dg_info_get(p, C.byref(info)))
+    return info
+
+
+def dg_rhs(p, u, rhs, stream=None):
+    _check(lib.dg_rhs(p, _ptr(u), _ptr(rhs), _stream(stream)))
+
+
+def dg_rk_step(p, u, res, t, dt, nsteps, stream=None):
+    _check(lib.dg_rk_step(p, _ptr(u), _ptr(res), float(t), float(dt), int(nsteps), _stream(stream)))
+
+
+def dg_pack(p, host_u, dev_u, stream=None):
+    host_u = np.ascontiguousarray(host_u, dtype=np.float64)
+    _check(lib.dg_pack(p, _ptr(host_u), _ptr(dev_u), _stream(stream)))
+
+
+def dg_unpack(p, dev_u, stream=None):
+    info = dg_info_get(p)
+    out = np.zeros((6, info.K, info.Np))
+    _check(lib.dg_unpack(p, _ptr(dev_u), _ptr(out), _stream(stream)))
+    return out
+
+
+def dg_nodes(p):
+    info = dg_info_get(p)
+    xyz = np.zeros((info.K, info.Np, 3))
+    _check(lib.dg_nodes(p, _ptr(xyz)))
+    return xyz
+
+
+def dg_destroy(p):
+    lib.dg_destroy(p)
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper
+# ---------------------------------------------------------------------------
+class Problem:
+    """Owns a dg_problem handle; allocates state arrays as torch tensors."""
+
+    def __init__(self, N, VX, EToV, precision="fp64", alpha=1.0):
+        self.handle = dg_setup_mesh(N, VX, EToV, precision, alpha)
+        self.info = dg_info_get(self.handle)
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.info.precision == DG_FP64 else torch.float32
+
+    def empty_state(self):
+        import torch
+        return torch.empty(self.info.state_elems, dtype=self.torch_dtype, device="cuda")
+
+    def zeros_state(self):
+        import torch
+        return torch.zeros(self.info.state_elems, dtype=self.torch_dtype, device="cuda")
+
+    def check_state(self, x, name="state"):
+        """Device state arrays must be contiguous CUDA tensors of the problem's
+        dtype with at least state_elems entries (the C ABI cannot see sizes)."""
+        if not (getattr(x, "is_cuda", False) and x.is_contiguous() and x.dtype == self.torch_dtype
+                and x.numel() >= self.info.state_elems):
+            raise ValueError(f"{name}: need a contiguous cuda {self.torch_dtype} tensor with >= "
+                             f"{self.info.state_elems} elements")
+        return x
+
+    def pack(self, host_u, dev_u=None, stream=None):
+        dev_u = self.empty_state() if dev_u is None else self.check_state(dev_u, "dev_u")
+        host_u = np.asarray(host_u, dtype=np.float64)
+        if host_u.shape != (6, self.info.K, self.info.Np):
+            raise ValueError(f"host_u must have shape (6, {self.info.K}, {self.info.Np})")
+        dg_pack(self.handle, host_u, dev_u, stream)
+        return dev_u
+
+    def unpack(self, dev_u, stream=None):
+        return dg_unpack(self.handle, self.check_state(dev_u, "dev_u"), stream)
+
+    def rhs(self, u, out, stream=None):
+        dg_rhs(self.handle, self.check_state(u, "u"), self.check_state(out, "out"), stream)
+
+    def rk_step(self, u, res, t, dt, nsteps=1, stream=None):
+        dg_rk_step(self.handle, self.check_state(u, "u"), self.check_state(res, "res"), t, dt, nsteps, stream)
+
+    def nodes(self):
+        return dg_nodes(self.handle)
+
+    def close(self):
+        if self.handle:
+            dg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,108 @@
+"""Host setup of the library (C++) against the oracle (NumPy), CPU only.
+
+The two build the reference element and the mesh data independently: nodes
+(same warp & blend reading), operators (LU inverse vs NumPy inverse),
+normals (inverse metric vs vertex cross products) and connectivity (lattice
+orientation codes vs coordinate matching).  They must agree to roundoff.
+Also checks the C ABI error paths that need no device.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import dg_inputs as I
+from oracle import mesh as Me
+from oracle import refelem as R
+
+dg = pytest.importorskip("paper_1211_0582_amd.dg", reason="libdg.so not built")
+
+
+def test_library_exports_every_declared_symbol():
+    import re
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    names = set()
+    for h in ("dg.h", "dg_host.h"):
+        text = open(os.path.join(root, "include", h)).read()
+        names |= set(re.findall(r"\b(dg_[a-z_]+)\s*\(", text))
+    names -= {"dg_status"}
+    assert names == set(dg.EXPORTED)
+    for n in names:
+        assert hasattr(dg.lib, n)
+
+
+@pytest.mark.parametrize("N", range(1, 10))
+def test_reference_nodes_match(N):
+    r, s, t = dg.dg_host_ref_nodes(N)
+    ro, so, to = R.nodes(N)
+    assert max(np.abs(r - ro).max(), np.abs(s - so).max(), np.abs(t - to).max()) < 1e-14
+
+
+@pytest.mark.parametrize("N", range(1, 10))
+def test_reference_operators_match(N):
+    ops = dg.dg_host_ref_operators(N)
+    re_ = R.ref_element(N)
+    scale = N * N
+    for name in ("Dr", "Ds", "Dt"):
+        assert np.abs(ops[name] - getattr(re_, name)).max() < 1e-12 * scale, name
+    assert np.abs(ops["LIFT"] - re_.LIFT).max() < 1e-12 * scale
+    assert np.array_equal(ops["Fmask"], re_.Fmask)
+    assert np.abs(ops["Mf"] - re_.Mf).max() < 1e-13
+
+
+@pytest.mark.parametrize("N,k,seed", [(3, 4, 0), (4, 3, 2), (1, 2, 1), (7, 1, 5)])
+def test_mesh_geometry_and_connectivity_match(N, k, seed):
+    VX, EToV = I.kuhn_cube(k, 0.1, seed)
+    h = dg.dg_host_mesh(N, VX, EToV)
+    m = Me.Mesh(N, VX, EToV)
+    met = np.stack([m.rx, m.ry, m.rz, m.sx, m.sy, m.sz, m.tx, m.ty, m.tz], axis=1)
+    assert np.allclose(h["metric"], met, rtol=1e-13, atol=1e-13 * np.abs(met).max())
+    assert np.allclose(h["J"], m.J, rtol=1e-13)
+    n = np.stack([m.nx, m.ny, m.nz], axis=2)
+    assert np.abs(h["face"][..., :3] - n).max() < 1e-13
+    assert np.allclose(h["face"][..., 3], m.Fscale, rtol=1e-12)
+    assert np.allclose(h["sJ"], m.sJ, rtol=1e-12)
+    # orientation-code neighbour map == coordinate-matched map
+    assert np.array_equal(h["vmapP"], m.vmapP)
+    assert np.sum(h["conn"] < 0) == m.n_boundary_faces == 12 * k * k
+
+
+def test_setup_rejects_bad_input_before_device_work():
+    VX, EToV = I.kuhn_cube(1, 0.0, 0)
+    bad = EToV.copy()
+    bad[2, [2, 3]] = bad[2, [3, 2]]          # flip orientation -> J < 0
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_host_mesh(2, VX, bad)
+    assert e.value.status == dg.DG_EMESH and "element 2" in str(e.value)
+    bad = EToV.copy()
+    bad[0, 0] = 999
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_host_mesh(2, VX, bad)
+    assert e.value.status == dg.DG_EMESH
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_host_mesh(10, VX, EToV)
+    assert e.value.status == dg.DG_EUNSUPPORTED
+    # a face shared by three elements
+    tri = np.concatenate([EToV, EToV[:1]])
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_host_mesh(2, VX, tri)
+    assert e.value.status == dg.DG_EMESH
+    # setup validates the same way (and the precision enum) before touching a GPU
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(2, VX, EToV, precision=7)
+    assert e.value.status == dg.DG_EINVAL
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(0, VX, EToV)
+    assert e.value.status == dg.DG_EUNSUPPORTED
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(2, VX, EToV, alpha=float("nan"))
+    assert e.value.status == dg.DG_EINVAL
+
+
+def test_null_arguments_rejected():
+    assert dg.lib.dg_rhs(None, None, None, None) == dg.DG_EINVAL
+    assert dg.lib.dg_rk_step(None, None, None, 0.0, 0.0, 1, None) == dg.DG_EINVAL
+    assert dg.lib.dg_info_get(None, None) == dg.DG_EINVAL
+    assert dg.lib.dg_setup_mesh(None, None) == dg.DG_EINVAL
+    dg.lib.dg_destroy(None)
