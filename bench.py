@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--rhs-reps", type=int, default=50)
+    ap.add_argument("--variant", default=None, help="kernel variant (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -120,6 +121,8 @@ def main():
     results = {}
     for prec in (args.precision, "fp32" if args.precision == "fp64" else "fp64"):
         p, u, mesh = make_problem(dg, k, N, prec)
+        if args.variant:
+            p.set_variant(args.variant)
         K, Np = p.info.K, p.info.Np
         s = p.info.elem_bytes
         du = p.pack(u)
@@ -148,13 +151,13 @@ def main():
             "ms_per_step": 1e3 * t_total / args.steps,
             "rhs_us": 1e6 * t_rhs,
             "rhs_gdofs": dofs / t_rhs / 1e9,
-            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                         "frac": achieved / peak, "traffic": None,
-                         "kernel": f"rhs_valu_kernel<{N},{'double' if prec == 'fp64' else 'float'}>",
+            "roofline": {"bound": "mfma" if p.variant == "mfma" else "alu", "achieved": achieved, "peak": peak,
+                         "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                         "kernel": f"rhs_{p.variant}_kernel<{N},{'double' if prec == 'fp64' else 'float'}>",
                          "algorithmic_flops_per_launch": flops,
                          "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K,
                          "hbm_GBs_algorithmic": bytes_per_element(N, s) * K / t_rhs / 1e9},
-            "K": K, "Np": Np,
+            "K": K, "Np": Np, "variant": p.variant,
         }
         p.close()
         del du, res, out
@@ -176,11 +179,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"jittered Kuhn cube {k}^3x6 tets (K={main_r['K']}), N={N} (Np={main_r['Np']}), "
                                f"PEC cavity + noise, upwind, LSERK(5,4) step = 5 RHS + 5 updates",
-                   "K": main_r["K"], "N": N, "precision": args.precision},
+                   "K": main_r["K"], "N": N, "precision": args.precision, "variant": main_r["variant"]},
         "roofline": main_r["roofline"],
         "rhs_us": main_r["rhs_us"],
         "rhs_gdofs": main_r["rhs_gdofs"],
-        "other_precision": {other: {kk: results[other][kk] for kk in ("value", "ms_per_step", "rhs_us", "rhs_gdofs", "roofline")}},
+        "other_precision": {other: {kk: results[other][kk] for kk in ("value", "ms_per_step", "rhs_us", "rhs_gdofs", "roofline", "variant")}},
     }
     if not args.no_cpu_baseline:
         VX, EToV = I.kuhn_cube(k, 0.1, 0)

@@ -93,6 +93,7 @@ typedef struct {
   double dt_cfl1;        /* 2 / ((N+1)^2 max Fscale): dt at CFL number 1          */
   double alpha;
   int64_t n_boundary_faces;
+  int32_t variant;       /* kernel variant in use (dg_variant_name)               */
 } dg_info;
 
 /* Builds the reference element, geometry, connectivity and uploads them to
@@ -112,6 +113,19 @@ dg_status dg_info_get(dg_problem p, dg_info* info);
  * stream.  Only the K*Np entries of each field of rhs are written.
  * Errors: DG_EINVAL (null pointer or u == rhs), DG_EHIP (launch failure). */
 dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
+
+/* Kernel variants of the right-hand side, all computing the same operator:
+ *   0 "valu": one workgroup per element tile on the vector ALUs;
+ *   1 "mfma": one wave per 16 elements, the contraction with
+ *             [Dr|Ds|Dt|LIFT] on the matrix cores, Runge-Kutta stage fused
+ *             into its epilogue.
+ * dg_setup_mesh picks "mfma" where it is built for (N, precision), else
+ * "valu".  dg_variant_name returns NULL outside 0 .. dg_variant_count()-1.
+ * dg_set_variant: DG_EINVAL (null p, v out of range), DG_EUNSUPPORTED (not
+ * built for this order and precision; the problem keeps its variant). */
+int32_t dg_variant_count(void);
+const char* dg_variant_name(int32_t v);
+dg_status dg_set_variant(dg_problem p, int32_t v);
 
 /* nsteps steps of the 5-stage low-storage RK4 scheme, in place:
  *   for each stage s: res <- A_s res + dt du/dt(u);  u <- u + B_s res,

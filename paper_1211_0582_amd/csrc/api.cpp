@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -26,9 +27,11 @@ struct dg_problem_s {
   void* d_ops = nullptr;
   uint8_t* d_nbr = nullptr;
   int32_t* d_fmask = nullptr;
-  void* d_scratch = nullptr;  // rhs buffer of dg_rk_step
+  void* d_frag = nullptr;     // MFMA A-fragments of [Dr|Ds|Dt|LIFT]
+  void* d_scratch = nullptr;  // rhs buffer (unfused stepping) / second state buffer (fused)
   std::vector<double> verts;  // K x 4 x 3 vertex coordinates (for dg_nodes)
-  dgd::RhsLauncher rhs = nullptr;
+  int variant = 0;
+  dgd::KernelSet ks;
 };
 
 namespace {
@@ -63,6 +66,7 @@ void free_problem(dg_problem p) {
   hipFree(p->d_ops);
   hipFree(p->d_nbr);
   hipFree(p->d_fmask);
+  hipFree(p->d_frag);
   hipFree(p->d_scratch);
   delete p;
 }
@@ -102,6 +106,29 @@ dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
   std::vector<int32_t> fm(re.fmask.begin(), re.fmask.end());
   DG_HIP(hipMemcpy(p->d_fmask, fm.data(), fm.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload fmask");
   DG_HIP(hipMemset(p->d_scratch, 0, size_t(p->state_elems) * sizeof(T)), "clear scratch");
+
+  // MFMA A-fragments: row block ib, depth step kg, lane l holds
+  // Op[16 ib + l % 16][depth column of (kg, l / 16)] with Op = [Dr|Ds|Dt|LIFT],
+  // each direction's depth padded from Np to a multiple of 4 with zeros.
+  const int Np4 = (Np + 3) & ~3, RB = (Np + 15) / 16, KSV = Np4 / 4, KSL = NF / 4, KS = 3 * KSV + KSL;
+  std::vector<T> frag(size_t(RB) * KS * 64, T(0));
+  for (int ib = 0; ib < RB; ++ib)
+    for (int kg = 0; kg < KS; ++kg)
+      for (int l = 0; l < 64; ++l) {
+        const int row = 16 * ib + (l & 15), q = l >> 4;
+        double v = 0.0;
+        if (row < Np) {
+          if (kg < 3 * KSV) {
+            const int j = 4 * (kg % KSV) + q;
+            if (j < Np) v = (*D[kg / KSV])(row, j);
+          } else {
+            v = re.LIFT(row, 4 * (kg - 3 * KSV) + q);
+          }
+        }
+        frag[(size_t(ib) * KS + kg) * 64 + l] = T(v);
+      }
+  DG_HIP(hipMalloc(&p->d_frag, frag.size() * sizeof(T)), "hipMalloc(fragments)");
+  DG_HIP(hipMemcpy(p->d_frag, frag.data(), frag.size() * sizeof(T), hipMemcpyHostToDevice), "upload fragments");
   return DG_OK;
 }
 
@@ -112,13 +139,19 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   a.geo = p->d_geo;
   a.conn = p->d_conn;
   a.ops = p->d_ops;
+  a.ops_frag = p->d_frag;
   a.nbr = p->d_nbr;
   a.fmask = p->d_fmask;
   a.K = p->K;
   a.fs = p->fs;
   a.alpha = p->alpha;
+  a.res = nullptr;
+  a.u_out = nullptr;
+  a.rk_a = a.rk_b = a.rk_dt = 0.0;
   return a;
 }
+
+const char* const kVariantNames[dgd::kVariantCount] = {"valu", "mfma"};
 
 }  // namespace
 
@@ -208,8 +241,14 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   p->state_elems = 6 * p->fs;
   p->n_boundary = hm.n_boundary;
   p->dt_cfl1 = 2.0 / ((desc->N + 1.0) * (desc->N + 1.0) * hm.max_fscale);
-  p->tile = dgd::rhs_tile(desc->N, desc->precision);
-  p->rhs = dgd::rhs_launcher(desc->N, desc->precision);
+  // Default kernel: the matrix-core variant where it is built, else the vector one.
+  p->variant = dgd::kVariantMfma;
+  p->ks = dgd::kernels(desc->N, desc->precision, p->variant);
+  if (!p->ks.rhs) {
+    p->variant = dgd::kVariantValu;
+    p->ks = dgd::kernels(desc->N, desc->precision, p->variant);
+  }
+  p->tile = p->ks.tile;
   hipGetDevice(&p->device);
   p->verts.resize(size_t(p->K) * 12);
   for (int64_t k = 0; k < p->K; ++k)
@@ -239,6 +278,23 @@ dg_status dg_info_get(dg_problem p, dg_info* info) {
   info->dt_cfl1 = p->dt_cfl1;
   info->alpha = p->alpha;
   info->n_boundary_faces = p->n_boundary;
+  info->variant = p->variant;
+  return DG_OK;
+}
+
+int32_t dg_variant_count(void) { return dgd::kVariantCount; }
+
+const char* dg_variant_name(int32_t v) { return (v >= 0 && v < dgd::kVariantCount) ? kVariantNames[v] : nullptr; }
+
+dg_status dg_set_variant(dg_problem p, int32_t v) {
+  clear_error();
+  if (!p) return fail(DG_EINVAL, "null problem");
+  if (v < 0 || v >= dgd::kVariantCount) return fail(DG_EINVAL, "variant out of range");
+  dgd::KernelSet k = dgd::kernels(p->N, p->precision, v);
+  if (!k.rhs) return fail(DG_EUNSUPPORTED, "variant not built for this order/precision");
+  p->variant = v;
+  p->ks = k;
+  p->tile = k.tile;
   return DG_OK;
 }
 
@@ -246,8 +302,8 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream) {
   clear_error();
   if (!p || !u || !rhs) return fail(DG_EINVAL, "null argument");
   if (u == rhs) return fail(DG_EINVAL, "u and rhs must not alias");
-  if (!p->rhs) return fail(DG_EUNSUPPORTED, "no kernel for this order/precision");
-  hipError_t e = p->rhs(rhs_args(p, u, rhs), static_cast<hipStream_t>(stream));
+  if (!p->ks.rhs) return fail(DG_EUNSUPPORTED, "no kernel for this order/precision");
+  hipError_t e = p->ks.rhs(rhs_args(p, u, rhs), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
   return DG_OK;
 }
@@ -260,10 +316,32 @@ dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int3
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t bytes = size_t(p->state_elems) * p->elem_bytes;
+  if (p->ks.rk) {
+    // Fused stages: each stage reads one state buffer and writes the other
+    // (neighbours still read the input during the stage), res in place.
+    dgd::RhsArgs ra = rhs_args(p, u, nullptr);
+    void* cur = u;
+    void* nxt = p->d_scratch;
+    ra.res = res;
+    ra.rk_dt = dt;
+    for (int32_t n = 0; n < nsteps; ++n)
+      for (int st = 0; st < 5; ++st) {
+        ra.u = cur;
+        ra.u_out = nxt;
+        ra.rk_a = kRkA[st];
+        ra.rk_b = kRkB[st];
+        hipError_t e = p->ks.rk(ra, s);
+        if (e != hipSuccess) return hip_fail(e, "fused stage kernel launch");
+        std::swap(cur, nxt);
+      }
+    if (cur != u) DG_HIP(hipMemcpyAsync(u, cur, bytes, hipMemcpyDeviceToDevice, s), "state copy");
+    return DG_OK;
+  }
   const dgd::RhsArgs ra = rhs_args(p, u, p->d_scratch);
   for (int32_t n = 0; n < nsteps; ++n)
     for (int st = 0; st < 5; ++st) {
-      hipError_t e = p->rhs(ra, s);
+      hipError_t e = p->ks.rhs(ra, s);
       if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
       dgd::UpdateArgs ua;
       ua.u = u;

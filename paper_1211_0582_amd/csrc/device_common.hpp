@@ -12,18 +12,23 @@ namespace dgd {
 //   [9+4f .. 12+4f] face f: nx ny nz Fscale
 constexpr int kGeoStride = 25;
 
-// Arguments of one right-hand-side evaluation.
+// Arguments of one right-hand-side evaluation (or one fused Runge-Kutta stage).
 struct RhsArgs {
   const void* u;          // state, [6][field_stride], element-major inside a field
-  void* rhs;              // output, same layout
+  void* rhs;              // output, same layout (right-hand-side mode)
   const void* geo;        // K x kGeoStride
   const int32_t* conn;    // K x 4, -1 wall, else nbr*32 + nbr_face*6 + orient
   const void* ops;        // Dr^T, Ds^T, Dt^T (Np x Np each, [j][i]), LIFT^T (4Nfp x Np, [m][i])
+  const void* ops_frag;   // [Dr|Ds|Dt|LIFT] as 16x4 MFMA A-fragments [row block][depth step][lane]
   const uint8_t* nbr;     // 4 x 24 x Nfp neighbour volume node per (face, code, j)
   const int32_t* fmask;   // 4 x Nfp
   int64_t K;
   int64_t fs;             // field stride in scalars
   double alpha;
+  // Runge-Kutta stage mode: res <- rk_a res + rk_dt rhs; u_out <- u + rk_b res.
+  void* res;
+  void* u_out;
+  double rk_a, rk_b, rk_dt;
 };
 
 // Arguments of one LSERK stage update: res <- a res + dt rhs; u <- u + b res.
@@ -38,10 +43,19 @@ struct UpdateArgs {
 
 using RhsLauncher = hipError_t (*)(const RhsArgs&, hipStream_t);
 
-// Launcher table: order N (1..9), precision 0 = FP64, 1 = FP32.
-RhsLauncher rhs_launcher(int N, int precision);
-// Elements per workgroup of the RHS kernel.
-int rhs_tile(int N, int precision);
+// Kernel variants of the right-hand side.
+enum Variant { kVariantValu = 0, kVariantMfma = 1, kVariantCount = 2 };
+
+struct KernelSet {
+  RhsLauncher rhs = nullptr;  // writes rhs
+  RhsLauncher rk = nullptr;   // fused Runge-Kutta stage (nullptr: rhs + update kernel)
+  int tile = 0;               // elements per workgroup
+  int frag_count = 0;         // scalars of the MFMA fragment array (0 if unused)
+};
+
+// Kernels for order N (1..9), precision (0 = FP64, 1 = FP32) and variant;
+// rhs == nullptr when the combination is not built.
+KernelSet kernels(int N, int precision, int variant);
 
 hipError_t launch_update(const UpdateArgs& a, int precision, hipStream_t s);
 

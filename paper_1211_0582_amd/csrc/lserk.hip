@@ -1,4 +1,4 @@
-// LSERK stage update and the per-order launcher table.
+// LSERK stage update and the per-order kernel table.
 //
 // Stage s of the five-stage low-storage RK4 scheme (Carpenter & Kennedy):
 //   res <- A_s res + dt rhs;  u <- u + B_s res.
@@ -9,9 +9,7 @@
 
 namespace dgd {
 
-#define DG_DECL(n)                               \
-  RhsLauncher rhs_launcher_n##n(int precision); \
-  int rhs_tile_n##n(int precision);
+#define DG_DECL(n) KernelSet kernels_n##n(int precision, int variant);
 DG_DECL(1)
 DG_DECL(2)
 DG_DECL(3)
@@ -23,33 +21,18 @@ DG_DECL(8)
 DG_DECL(9)
 #undef DG_DECL
 
-RhsLauncher rhs_launcher(int N, int p) {
+KernelSet kernels(int N, int p, int v) {
   switch (N) {
-    case 1: return rhs_launcher_n1(p);
-    case 2: return rhs_launcher_n2(p);
-    case 3: return rhs_launcher_n3(p);
-    case 4: return rhs_launcher_n4(p);
-    case 5: return rhs_launcher_n5(p);
-    case 6: return rhs_launcher_n6(p);
-    case 7: return rhs_launcher_n7(p);
-    case 8: return rhs_launcher_n8(p);
-    case 9: return rhs_launcher_n9(p);
-    default: return nullptr;
-  }
-}
-
-int rhs_tile(int N, int p) {
-  switch (N) {
-    case 1: return rhs_tile_n1(p);
-    case 2: return rhs_tile_n2(p);
-    case 3: return rhs_tile_n3(p);
-    case 4: return rhs_tile_n4(p);
-    case 5: return rhs_tile_n5(p);
-    case 6: return rhs_tile_n6(p);
-    case 7: return rhs_tile_n7(p);
-    case 8: return rhs_tile_n8(p);
-    case 9: return rhs_tile_n9(p);
-    default: return 0;
+    case 1: return kernels_n1(p, v);
+    case 2: return kernels_n2(p, v);
+    case 3: return kernels_n3(p, v);
+    case 4: return kernels_n4(p, v);
+    case 5: return kernels_n5(p, v);
+    case 6: return kernels_n6(p, v);
+    case 7: return kernels_n7(p, v);
+    case 8: return kernels_n8(p, v);
+    case 9: return kernels_n9(p, v);
+    default: return KernelSet{};
   }
 }
 

@@ -21,7 +21,8 @@ PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32}
 
 #: every symbol the public headers declare
 EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",
-            "dg_destroy", "dg_last_error", "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
+            "dg_destroy", "dg_last_error", "dg_variant_count", "dg_variant_name", "dg_set_variant",
+            "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
 
 
 class DgError(RuntimeError):
@@ -40,7 +41,7 @@ class Info(C.Structure):
     _fields_ = [("N", C.c_int32), ("Np", C.c_int32), ("Nfp", C.c_int32), ("precision", C.c_int32),
                 ("K", C.c_int64), ("field_stride", C.c_int64), ("state_elems", C.c_int64),
                 ("elem_bytes", C.c_int32), ("tile_elems", C.c_int32), ("dt_cfl1", C.c_double),
-                ("alpha", C.c_double), ("n_boundary_faces", C.c_int64)]
+                ("alpha", C.c_double), ("n_boundary_faces", C.c_int64), ("variant", C.c_int32)]
 
 
 def _load():
@@ -62,6 +63,9 @@ def _load():
         "dg_nodes": (C.c_int, [P, P]),
         "dg_destroy": (None, [P]),
         "dg_last_error": (C.c_char_p, []),
+        "dg_variant_count": (C.c_int32, []),
+        "dg_variant_name": (C.c_char_p, [C.c_int32]),
+        "dg_set_variant": (C.c_int, [P, C.c_int32]),
         "dg_host_ref_nodes": (C.c_int, [C.c_int32, P, P, P]),
         "dg_host_ref_operators": (C.c_int, [C.c_int32, P, P, P, P, P, P]),
         "dg_host_mesh": (C.c_int, [C.c_int32, C.c_int64, P, C.c_int64, P, P, P, P, P, P, P]),
@@ -190,6 +194,28 @@ def dg_destroy(p):
     lib.dg_destroy(p)
 
 
+def dg_variant_count():
+    return int(lib.dg_variant_count())
+
+
+def dg_variant_name(v):
+    n = lib.dg_variant_name(int(v))
+    return None if n is None else n.decode()
+
+
+def variant_id(name):
+    for v in range(dg_variant_count()):
+        if dg_variant_name(v) == name:
+            return v
+    raise ValueError(f"unknown variant {name!r}")
+
+
+def dg_set_variant(p, v):
+    if isinstance(v, str):
+        v = variant_id(v)
+    _check(lib.dg_set_variant(p, int(v)))
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrapper
 # ---------------------------------------------------------------------------
@@ -241,6 +267,14 @@ class Problem:
 
     def nodes(self):
         return dg_nodes(self.handle)
+
+    def set_variant(self, v):
+        dg_set_variant(self.handle, v)
+        self.info = dg_info_get(self.handle)
+
+    @property
+    def variant(self):
+        return dg_variant_name(self.info.variant)
 
     def close(self):
         if self.handle:
