@@ -95,14 +95,18 @@ dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
   DG_HIP(hipMalloc(&p->d_geo, geo.size() * sizeof(T)), "hipMalloc(geometry)");
   DG_HIP(hipMalloc(&p->d_conn, hm.conn.size() * sizeof(int32_t)), "hipMalloc(connectivity)");
   DG_HIP(hipMalloc(&p->d_ops, ops.size() * sizeof(T)), "hipMalloc(operators)");
-  DG_HIP(hipMalloc(&p->d_nbr, re.nbr_node.size()), "hipMalloc(neighbour table)");
+  // The orientation table is padded to a multiple of 16 bytes (kernels copy
+  // it with 16-byte loads).
+  std::vector<uint8_t> nbr(re.nbr_node);
+  nbr.resize((nbr.size() + 15) / 16 * 16, 0);
+  DG_HIP(hipMalloc(&p->d_nbr, nbr.size()), "hipMalloc(neighbour table)");
   DG_HIP(hipMalloc(&p->d_fmask, re.fmask.size() * sizeof(int32_t)), "hipMalloc(fmask)");
   DG_HIP(hipMalloc(&p->d_scratch, size_t(p->state_elems) * sizeof(T)), "hipMalloc(scratch)");
   DG_HIP(hipMemcpy(p->d_geo, geo.data(), geo.size() * sizeof(T), hipMemcpyHostToDevice), "upload geometry");
   DG_HIP(hipMemcpy(p->d_conn, hm.conn.data(), hm.conn.size() * sizeof(int32_t), hipMemcpyHostToDevice),
          "upload connectivity");
   DG_HIP(hipMemcpy(p->d_ops, ops.data(), ops.size() * sizeof(T), hipMemcpyHostToDevice), "upload operators");
-  DG_HIP(hipMemcpy(p->d_nbr, re.nbr_node.data(), re.nbr_node.size(), hipMemcpyHostToDevice), "upload table");
+  DG_HIP(hipMemcpy(p->d_nbr, nbr.data(), nbr.size(), hipMemcpyHostToDevice), "upload table");
   std::vector<int32_t> fm(re.fmask.begin(), re.fmask.end());
   DG_HIP(hipMemcpy(p->d_fmask, fm.data(), fm.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload fmask");
   DG_HIP(hipMemset(p->d_scratch, 0, size_t(p->state_elems) * sizeof(T)), "clear scratch");

@@ -67,11 +67,15 @@ struct MfmaShape {
   static constexpr int KS = 3 * KSV + KSL;
   static constexpr int TS = 17;               // LDS row stride (16 elements + 1)
   static constexpr int frag_count = RB * KS * 64;
+  // The LDS tile holds the fields [c][Np4][TS] first, then the fluxes
+  // [c][NF][TS], then the output staging [c][16][Np].
+  static constexpr int ROWS = Np4 > NF ? Np4 : NF;
+  static constexpr int TILE = 6 * ROWS * TS;
 };
 
 template <int N, typename T>
 constexpr size_t mfma_lds_bytes() {
-  return size_t(6) * MfmaShape<N>::Np4 * MfmaShape<N>::TS * sizeof(T);
+  return size_t(MfmaShape<N>::TILE) * sizeof(T);
 }
 
 // Whether the MFMA variant is built for (N, T): the LDS tile and the
@@ -81,100 +85,64 @@ constexpr bool mfma_supported() {
   return mfma_lds_bytes<N, T>() <= 65536 && MfmaShape<N>::RB * 3 * 4 * sizeof(T) / 4 <= 128;
 }
 
-// Workgroup = two waves sharing one tile of 16 elements.  Wave h = 0 produces
-// the E equations (curl H + LIFT fE), wave h = 1 the H equations
-// (-curl E + LIFT fH).  Both run the same code with the field roles swapped:
-// with V = H, (P, Q) = (dE, dH) for h = 0 and V = -E, (P, Q) = (dH, -dE) for
-// h = 1, the volume operand is X_d = m_d x V and the flux is
-// f = 1/2 Fscale [ -n x Q + alpha (n (n.P) - P) ].
-template <int N, typename T, bool RK>
-__global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
+// Raw buffer loads: a 128-bit resource (base, size) in SGPRs plus a 32-bit
+// byte offset per lane and a wave-uniform byte offset, so gathers and operator
+// fragments need no 64-bit address arithmetic on the vector ALU.  Offsets at
+// or beyond the resource size read as zero instead of faulting.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+// State shared by the two waves of a workgroup.
+template <int N, typename T>
+struct MfmaTile {
+  using S = MfmaShape<N>;
+  T su[S::TILE];                      // fields [c][j][e], then fluxes [c][m][e], then output
+  int16_t fmask[S::NF];
+  alignas(16) uint8_t nbr[(4 * 24 * S::Nfp + 15) / 16 * 16];
+  int32_t code[16 * 4];               // face codes of the tile's elements
+  T face[16 * 4 * 4];                 // nx, ny, nz, Fscale / 2 per (element, face)
+};
+
+// Contraction of one wave.  H = 0 produces the E equations (curl H + LIFT fE),
+// H = 1 the H equations (-curl E + LIFT fH).  With V = H, (P, Q) = (dE, dH)
+// for H = 0 and V = -E, (P, Q) = (dH, -dE) for H = 1, the volume operand is
+// X_d = m_d x V and the flux f = 1/2 Fscale [ -n x Q + alpha (n (n.P) - P) ].
+template <int N, typename T, int H, typename FluxPhase>
+__device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&mr)[9], int lane, int64_t k0,
+                                 typename Mfma16<T>::acc (&acc)[MfmaShape<N>::RB][3], FluxPhase&& flux_phase) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
-  constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, KSV = S::KSV, KSL = S::KSL;
+  constexpr int Np4 = S::Np4, NF = S::NF, RB = S::RB, KSV = S::KSV, KSL = S::KSL;
   constexpr int KS = S::KS, TS = S::TS;
-  __shared__ T su[6 * Np4 * TS];
-  __shared__ int16_t s_fmask[NF];
-  __shared__ uint8_t s_nbr[4 * 24 * Nfp];
-  __shared__ int32_t s_code[16 * 4];   // face codes of the tile's elements
-  __shared__ T s_face[16 * 4 * 4];     // nx, ny, nz, Fscale / 2 per (element, face)
-
-  const T* __restrict__ u = static_cast<const T*>(a.u);
-  const T* __restrict__ geo = static_cast<const T*>(a.geo);
-  const T* __restrict__ frag = static_cast<const T*>(a.ops_frag);
-  const int64_t fs = a.fs;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int h = tid >> 6;             // 0: E equations, 1: H equations
+  constexpr uint32_t sz = sizeof(T);
   const int e = lane & 15, q = lane >> 4;
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag, uint32_t(RB * KS * 64) * sz);
 
-  // XCD-aware tile: workgroup b runs on XCD b % 8; give each XCD a contiguous range.
-  const int64_t nt = (a.K + 15) / 16;
-  const int64_t per = (nt + 7) / 8;
-  const int64_t tile = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (tile >= nt) return;
-  const int64_t k0 = tile * 16;
-  const int ne = int((a.K - k0) < 16 ? (a.K - k0) : 16);
-  const bool live = e < ne;
-  const int64_t ke = k0 + (live ? e : 0);
-
-  // Metric of this lane's element in registers; face records and tables in LDS.
-  T mr[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) mr[i] = live ? geo[ke * kGeoStride + i] : T(0);
-  if (tid < 64) {
-    const int ee = tid >> 2, f = tid & 3;  // 16 elements x 4 faces
-    const bool lv = ee < ne;
-    const int64_t kk = k0 + (lv ? ee : 0);
-    s_code[tid] = lv ? a.conn[kk * 4 + f] : -1;
-    const T* gf = geo + kk * kGeoStride + 9 + 4 * f;
-    s_face[4 * tid + 0] = lv ? gf[0] : T(0);
-    s_face[4 * tid + 1] = lv ? gf[1] : T(0);
-    s_face[4 * tid + 2] = lv ? gf[2] : T(0);
-    s_face[4 * tid + 3] = lv ? T(0.5) * gf[3] : T(0);
-  }
-  for (int i = tid; i < NF; i += 128) s_fmask[i] = int16_t(a.fmask[i]);
-  for (int i = tid; i < 4 * 24 * Nfp; i += 128) s_nbr[i] = a.nbr[i];
-
-  // 1. fields of the tile -> LDS [c][j][e] (global reads contiguous per field)
-  constexpr int kLoadIters = (16 * Np + 127) / 128;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    const T* src = u + c * fs + k0 * Np;
-#pragma unroll
-    for (int it = 0; it < kLoadIters; ++it) {
-      const int idx = tid + 128 * it;
-      if (idx < 16 * Np) {
-        const int ee = idx / Np, j = idx - ee * Np;
-        su[(c * Np4 + j) * TS + ee] = (ee < ne) ? src[idx] : T(0);
-      }
-    }
-    if constexpr (Np4 > Np) {
-      for (int idx = tid; idx < (Np4 - Np) * 16; idx += 128)
-        su[(c * Np4 + Np + idx / 16) * TS + (idx & 15)] = T(0);
-    }
-  }
-  __syncthreads();
-
-  acc_t acc[RB][3];
 #pragma unroll
   for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[ib][c] = acc_t{0, 0, 0, 0};
 
-  // Field roles of this wave: V (volume) = fields vb.. with sign vs; own
-  // outputs are fields 3h .. 3h+2.
-  const int vb = h ? 0 : 3;           // V = H (h = 0) or -E (h = 1)
-  const T vs = h ? T(-1) : T(1);
-
-  // Software pipeline: every global load is issued kPre depth steps before its
-  // use (operator fragments over the whole depth, neighbour traces).
-  constexpr int kPre = 2;
+  // Software pipeline: global loads are issued kPre depth steps before use
+  // (one step when the accumulators already take most of the registers).
+  constexpr int kPre = RB >= 6 ? 1 : 2;
   constexpr int NV = 3 * KSV;  // volume depth steps, ordered (ks, d)
+  const uint32_t lane_off = uint32_t(lane) * sz;
   auto frag_of = [&](int step, int ib) -> T {
     const int kg = step < NV ? (step % 3) * KSV + step / 3 : 3 * KSV + (step - NV);
-    return frag[(ib * KS + kg) * 64 + lane];
+    return buf_load<T>(rf, lane_off, uint32_t((ib * KS + kg) * 64) * sz);
   };
   T Abuf[kPre + 1][RB];
 #pragma unroll
@@ -182,13 +150,15 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
 #pragma unroll
     for (int ib = 0; ib < RB; ++ib) Abuf[s][ib] = frag_of(s, ib);
 
-  // 2. volume: X_d = m_d x V at node j = 4 ks + q of element e
+  // Volume: X_d = m_d x V at node j = 4 ks + q of element e.
+  constexpr int vb = H ? 0 : 3;
+  const T vs = H ? T(-1) : T(1);
 #pragma unroll
   for (int ks = 0; ks < KSV; ++ks) {
     const int j = 4 * ks + q;
     T v[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[c] = vs * su[((vb + c) * Np4 + j) * TS + e];
+    for (int c = 0; c < 3; ++c) v[c] = vs * t.su[((vb + c) * Np4 + j) * TS + e];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int step = 3 * ks + d;
@@ -208,24 +178,11 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
     }
   }
 
-  // 3. lifting, flux evaluated in B-fragment layout at face node m = 4 ks + q.
-  auto gather = [&](int ks, T (&out)[6]) {
-    const int m = 4 * ks + q;
-    const int f = m / Nfp;
-    const int jj = m - f * Nfp;
-    const int32_t cf = s_code[4 * e + f];
-    const int64_t g = cf >= 0 ? int64_t(cf >> 5) * Np + s_nbr[(f * 24 + (cf & 31)) * Nfp + jj] : ke * Np;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) out[c] = u[c * fs + g];
-  };
-  T Pbuf[kPre + 1][6];
-#pragma unroll
-  for (int s = 0; s < kPre; ++s) gather(s, Pbuf[s]);
-
-  const T alpha = T(a.alpha);
-  const int pb = h ? 3 : 0;            // P = jump of fields pb..pb+2
-  const int qb = h ? 0 : 3;            // Q = qs * jump of fields qb..qb+2
-  const T qs = h ? T(-1) : T(1);
+  // Lifting: F (already scaled by Fscale / 2) comes from the LDS flux tile,
+  // which the workgroup's flux phase writes between the two phases.
+  flux_phase(t, k0);
+  __syncthreads();
+  constexpr int cb = H ? 3 : 0;
 #pragma unroll
   for (int ks = 0; ks < KSL; ++ks) {
     const int step = NV + ks;
@@ -233,44 +190,188 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
 #pragma unroll
       for (int ib = 0; ib < RB; ++ib) Abuf[(step + kPre) % (kPre + 1)][ib] = frag_of(step + kPre, ib);
     }
-    if (ks + kPre < KSL) gather(ks + kPre, Pbuf[(ks + kPre) % (kPre + 1)]);
     const int m = 4 * ks + q;
-    const int f = m / Nfp;
-    const int own = s_fmask[m];
-    const bool wall = s_code[4 * e + f] < 0;
-    T d[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const T em = su[(c * Np4 + own) * TS + e];
-      // wall: E+ = -E-, H+ = H-  =>  dE = 2 E-, dH = 0
-      const T ep = wall ? (c < 3 ? -em : em) : Pbuf[ks % (kPre + 1)][c];
-      d[c] = em - ep;
-    }
-    T P[3], Q[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      P[c] = h ? d[3 + c] : d[c];
-      Q[c] = qs * (h ? d[c] : d[3 + c]);
-    }
-    (void)pb;
-    (void)qb;
-    const T* fr = &s_face[4 * (4 * e + f)];
-    const T nx = fr[0], ny = fr[1], nz = fr[2], sc = fr[3];
-    const T nP = nx * P[0] + ny * P[1] + nz * P[2];
     T F[3];
-    F[0] = sc * (-(ny * Q[2] - nz * Q[1]) + alpha * (nx * nP - P[0]));
-    F[1] = sc * (-(nz * Q[0] - nx * Q[2]) + alpha * (ny * nP - P[1]));
-    F[2] = sc * (-(nx * Q[1] - ny * Q[0]) + alpha * (nz * nP - P[2]));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[c] = t.su[((cb + c) * NF + m) * TS + e];
 #pragma unroll
     for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[ib][c] = M::mac(Abuf[step % (kPre + 1)][ib], F[c], acc[ib][c]);
   }
+}
 
-  // 4. epilogue through LDS: [c][e][i] for this wave's three fields, then
+// Workgroup = two waves sharing one tile of 16 elements; wave h = 0 produces
+// the E equations, wave h = 1 the H equations (see mfma_wave).
+template <int N, typename T, bool RK>
+__global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
+  using S = MfmaShape<N>;
+  using M = Mfma16<T>;
+  using acc_t = typename M::acc;
+  constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, TS = S::TS;
+  __shared__ MfmaTile<N, T> t;
+
+  const int64_t fs = a.fs;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int h = tid >> 6;
+  const int e = lane & 15, q = lane >> 4;
+
+  // XCD-aware tile: workgroup b runs on XCD b % 8; give each XCD a contiguous range.
+  const int64_t nt = (a.K + 15) / 16;
+  const int64_t per = (nt + 7) / 8;
+  const int64_t tile = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= nt) return;
+  const int64_t k0 = tile * 16;
+  const int ne = int((a.K - k0) < 16 ? (a.K - k0) : 16);
+  const bool live = e < ne;
+  const int64_t ke = k0 + (live ? e : 0);
+
+  // All loads of the prologue are unconditional raw buffer loads: lanes past
+  // the end of a ragged tile use an out-of-range offset and read zero, so no
+  // load sits behind a branch and all of them are in flight together.
+  constexpr uint32_t sz = sizeof(T);
+  constexpr uint32_t kOob = 0x80000000u;
+  const __amdgpu_buffer_rsrc_t rg = make_rsrc(a.geo, uint32_t(a.K) * kGeoStride * sz);
+  const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.conn, uint32_t(a.K) * 4 * 4);
+  const __amdgpu_buffer_rsrc_t ru = make_rsrc(a.u, 6u * uint32_t(fs) * sz);
+
+  // Metric of this lane's element in registers; face records and tables in LDS.
+  T mr[9];
+  {
+    const uint32_t go = live ? uint32_t(ke * kGeoStride) * sz : kOob;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) mr[i] = buf_load<T>(rg, go, i * sz);
+  }
+  if (tid < 64) {
+    const int ee = tid >> 2, f = tid & 3;  // 16 elements x 4 faces
+    const bool lv = ee < ne;
+    const uint32_t go = lv ? uint32_t((k0 + ee) * kGeoStride + 9 + 4 * f) * sz : kOob;
+    const int32_t cf = __builtin_bit_cast(int32_t, __builtin_amdgcn_raw_buffer_load_b32(
+                                                       rc, lv ? uint32_t((k0 + ee) * 4 + f) * 4 : kOob, 0, 0));
+    t.code[tid] = lv ? cf : -1;
+    t.face[4 * tid + 0] = buf_load<T>(rg, go, 0);
+    t.face[4 * tid + 1] = buf_load<T>(rg, go, sz);
+    t.face[4 * tid + 2] = buf_load<T>(rg, go, 2 * sz);
+    t.face[4 * tid + 3] = T(0.5) * buf_load<T>(rg, go, 3 * sz);
+  }
+  // Tables: fully unrolled, 16-byte loads for the orientation table (its
+  // device copy is padded to a multiple of 16 bytes), so every load is in
+  // flight at once.
+  constexpr int kFmaskIters = (NF + 127) / 128;
+#pragma unroll
+  for (int it = 0; it < kFmaskIters; ++it) {
+    const int i = tid + 128 * it;
+    if (i < NF) t.fmask[i] = int16_t(a.fmask[i]);
+  }
+  constexpr int kNbrVec = (4 * 24 * Nfp + 15) / 16;
+  constexpr int kNbrIters = (kNbrVec + 127) / 128;
+#pragma unroll
+  for (int it = 0; it < kNbrIters; ++it) {
+    const int i = tid + 128 * it;
+    if (i < kNbrVec) reinterpret_cast<uint4*>(t.nbr)[i] = reinterpret_cast<const uint4*>(a.nbr)[i];
+  }
+
+  // Fields of the tile -> LDS [c][j][e] (global reads contiguous per field).
+  constexpr int kLoadIters = (16 * Np + 127) / 128;
+  T tv[kLoadIters][6];
+#pragma unroll
+  for (int it = 0; it < kLoadIters; ++it) {
+    const int idx = tid + 128 * it;
+    const bool in = idx < ne * Np;
+    const uint32_t vo = in ? uint32_t(k0 * Np + idx) * sz : kOob;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tv[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
+  }
+#pragma unroll
+  for (int it = 0; it < kLoadIters; ++it) {
+    const int idx = tid + 128 * it;
+    const int ee = idx / Np, j = idx - ee * Np;
+    if (idx < 16 * Np) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t.su[(c * Np4 + j) * TS + ee] = tv[it][c];
+    }
+  }
+  if constexpr (Np4 > Np) {
+    for (int idx = tid; idx < 6 * (Np4 - Np) * 16; idx += 128) {
+      const int c = idx / ((Np4 - Np) * 16), r = idx - c * ((Np4 - Np) * 16);
+      t.su[(c * Np4 + Np + r / 16) * TS + (r & 15)] = T(0);
+    }
+  }
+  __syncthreads();
+
+  // Flux phase, run by all 128 lanes between the volume and the lift phases:
+  // one lane per (element, face node) pair, each flux evaluated once.  All
+  // exterior traces of a lane are gathered at once; own traces are read from
+  // the field tile, which is then overwritten by the fluxes [c][m][e].
+  constexpr int kPairs = 16 * NF;
+  constexpr int kFluxIters = (kPairs + 127) / 128;
+  const T alpha = T(a.alpha);
+  auto flux_phase = [&](MfmaTile<N, T>& tt, int64_t) {
+    T gx[kFluxIters][6];
+#pragma unroll
+    for (int it = 0; it < kFluxIters; ++it) {
+      const int pr = tid + 128 * it;
+      const int ee = pr & 15, m = pr >> 4;
+      const int f = m / Nfp, jj = m - f * Nfp;
+      const int32_t cf = (pr < kPairs) ? tt.code[4 * ee + f] : -1;
+      // interior: neighbour node; wall: own node (mirror applied below); dead: zero
+      uint32_t vo = kOob;
+      if (pr < kPairs && ee < ne)
+        vo = uint32_t(cf >= 0 ? int64_t(cf >> 5) * Np + tt.nbr[(f * 24 + (cf & 31)) * Nfp + jj]
+                              : (k0 + ee) * Np + tt.fmask[m]) * sz;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) gx[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
+    }
+    T fl[kFluxIters][6];
+#pragma unroll
+    for (int it = 0; it < kFluxIters; ++it) {
+      const int pr = tid + 128 * it;
+      const int ee = pr & 15, m = pr >> 4;
+      if (pr < kPairs) {
+        const int f = m / Nfp;
+        const int own = tt.fmask[m];
+        const T se = tt.code[4 * ee + f] < 0 ? T(-1) : T(1);  // wall: E+ = -E-, H+ = H-
+        T d[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const T em = tt.su[(c * Np4 + own) * TS + ee];
+          d[c] = c < 3 ? em - se * gx[it][c] : em - gx[it][c];
+        }
+        const T* fr = &tt.face[4 * (4 * ee + f)];
+        const T nx = fr[0], ny = fr[1], nz = fr[2], sc = fr[3];
+        const T ndE = nx * d[0] + ny * d[1] + nz * d[2];
+        const T ndH = nx * d[3] + ny * d[4] + nz * d[5];
+        fl[it][0] = sc * (-(ny * d[5] - nz * d[4]) + alpha * (nx * ndE - d[0]));
+        fl[it][1] = sc * (-(nz * d[3] - nx * d[5]) + alpha * (ny * ndE - d[1]));
+        fl[it][2] = sc * (-(nx * d[4] - ny * d[3]) + alpha * (nz * ndE - d[2]));
+        fl[it][3] = sc * ((ny * d[2] - nz * d[1]) + alpha * (nx * ndH - d[3]));
+        fl[it][4] = sc * ((nz * d[0] - nx * d[2]) + alpha * (ny * ndH - d[4]));
+        fl[it][5] = sc * ((nx * d[1] - ny * d[0]) + alpha * (nz * ndH - d[5]));
+      }
+    }
+    __syncthreads();  // every own-trace read is done before the tile is overwritten
+#pragma unroll
+    for (int it = 0; it < kFluxIters; ++it) {
+      const int pr = tid + 128 * it;
+      const int ee = pr & 15, m = pr >> 4;
+      if (pr < kPairs) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tt.su[(c * NF + m) * TS + ee] = fl[it][c];
+      }
+    }
+  };
+
+  acc_t acc[RB][3];
+  if (h == 0)
+    mfma_wave<N, T, 0>(a, t, mr, lane, k0, acc, flux_phase);
+  else
+    mfma_wave<N, T, 1>(a, t, mr, lane, k0, acc, flux_phase);
+
+  // Epilogue through LDS: [c][e][i] for this wave's three fields, then
   // contiguous stores per field.
   __syncthreads();
-  T* so = su + h * (3 * 16 * Np);
+  T* so = t.su + h * (3 * 16 * Np);
 #pragma unroll
   for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
@@ -295,6 +396,7 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
   } else {
     T* __restrict__ res = static_cast<T*>(a.res);
     T* __restrict__ uo = static_cast<T*>(a.u_out);
+    const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.res, 6u * uint32_t(fs) * sz);
     const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -302,9 +404,10 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
 #pragma unroll
       for (int it = 0; it < kOutIters; ++it) {
         const int idx = lane + 64 * it;
-        const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
-        rv[it] = idx < nv ? res[g] : T(0);
-        uv[it] = idx < nv ? u[g] : T(0);
+        const uint32_t vo = idx < nv ? uint32_t(k0 * Np + idx) * sz : kOob;
+        const uint32_t so_ = uint32_t((3 * h + c) * fs) * sz;
+        rv[it] = buf_load<T>(rr, vo, so_);
+        uv[it] = buf_load<T>(ru, vo, so_);
       }
 #pragma unroll
       for (int it = 0; it < kOutIters; ++it) {
