@@ -107,6 +107,10 @@ def main():
     ap.add_argument("--rhs-reps", type=int, default=50)
     ap.add_argument("--variant", default=None, help="kernel variant (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one torch copy of 256 MiB (scale for the HBM traffic counters)")
+    ap.add_argument("--traffic-file", default=None,
+                    help="traffic summary written from rocprofv3 --pmc runs (default: profiles/rhs_traffic_k<k>_n<N>.txt)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path is not part of this build "
@@ -116,8 +120,17 @@ def main():
     import torch
     from paper_1211_0582_amd import dg
 
+    from paper_1211_0582_amd import profiling
+
     torch.cuda.set_device(0)
     N, k = args.order, args.k
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    traffic_file = args.traffic_file or os.path.join(ROOT, "profiles", f"rhs_traffic_k{k}_n{N}.txt")
     results = {}
     for prec in (args.precision, "fp32" if args.precision == "fp64" else "fp64"):
         p, u, mesh = make_problem(dg, k, N, prec)
@@ -146,14 +159,18 @@ def main():
         flops = flops_per_element(N) * K
         peak = PEAKS["fp64_TFs"] if prec == "fp64" else PEAKS["fp32_TFs"]
         achieved = flops / t_rhs / 1e12
+        tname = "double" if prec == "fp64" else "float"
+        kname = (f"void dgd::rhs_mfma_kernel<{N}, {tname}, false>(dgd::RhsArgs)" if p.variant == "mfma"
+                 else f"void dgd::rhs_valu_kernel<{N}, {tname}>(dgd::RhsArgs)")
+        traffic = profiling.read_traffic(traffic_file, kname)
         results[prec] = {
             "value": 5 * dofs * args.steps / t_total / 1e9,
             "ms_per_step": 1e3 * t_total / args.steps,
             "rhs_us": 1e6 * t_rhs,
             "rhs_gdofs": dofs / t_rhs / 1e9,
             "roofline": {"bound": "mfma" if p.variant == "mfma" else "alu", "achieved": achieved, "peak": peak,
-                         "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                         "kernel": f"rhs_{p.variant}_kernel<{N},{'double' if prec == 'fp64' else 'float'}>",
+                         "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                         "kernel": kname,
                          "algorithmic_flops_per_launch": flops,
                          "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K,
                          "hbm_GBs_algorithmic": bytes_per_element(N, s) * K / t_rhs / 1e9},

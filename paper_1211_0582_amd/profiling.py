@@ -1,0 +1,117 @@
+"""Summaries of rocprofv3 output for the benchmark's kernels.
+
+``python -m paper_1211_0582_amd.profiling stats <kernel_stats.csv> <out.txt> <command...>``
+    writes the per-kernel duration table of a ``--kernel-trace --stats`` run.
+``python -m paper_1211_0582_amd.profiling traffic <fetch_dir> <write_dir> <out.txt> <substr> <copy_bytes> <command...>``
+    writes the HBM traffic per dispatch of the kernels whose name contains
+    ``substr``: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two
+    ``--pmc`` runs, each scaled by what the same counter reads for a plain
+    copy of ``copy_bytes`` bytes in the same run.
+
+The traffic summary records a hash of the kernel sources; ``bench.py`` only
+reports the traffic while the sources still hash to that value.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    """sha256 over the HIP/C++ sources of the library (sorted by name)."""
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if path.endswith((".hip", ".hpp", ".cpp")):
+            h.update(os.path.basename(path).encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def stats_summary(csv_path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(csv_path)))
+    out = [f"command: {command}", "", f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    for r in rows:
+        out.append(f"{r['Name'][:70]:70s} {r['Calls']:>6s} {float(r['AverageNs']) / 1e3:10.2f} "
+                   f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def _counter_rows(d: str):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    rows = []
+    for f in files:
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def _per_kernel(rows, counter):
+    acc = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return acc
+
+
+def traffic_summary(fetch_dir, write_dir, substr, copy_bytes, command):
+    fetch = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
+    write = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+    copy_f = [v for k, vs in fetch.items() if "copy" in k.lower() for v in vs]
+    copy_w = [v for k, vs in write.items() if "copy" in k.lower() for v in vs]
+    if not copy_f or not copy_w:
+        raise RuntimeError("no calibration copy kernel in the counter runs")
+    kib = copy_bytes / 1024.0
+    f_scale = kib / max(copy_f)
+    w_scale = kib / max(copy_w)
+    out = [f"command: {command}", f"source_sha256: {source_hash()}",
+           f"calibration: copy of {copy_bytes} bytes reads FETCH_SIZE {max(copy_f):.1f} KiB, "
+           f"WRITE_SIZE {max(copy_w):.1f} KiB -> scale {f_scale:.4f} / {w_scale:.4f}", ""]
+    for name in sorted(fetch):
+        if substr not in name:
+            continue
+        fv = fetch[name][1:] if len(fetch[name]) > 1 else fetch[name]
+        wv = write.get(name, [0.0])
+        wv = wv[1:] if len(wv) > 1 else wv
+        fb = sum(fv) / len(fv) * f_scale * 1024.0
+        wb = sum(wv) / len(wv) * w_scale * 1024.0
+        out.append(f"kernel: {name}")
+        out.append(f"  fetch_bytes_per_dispatch: {fb:.0f}")
+        out.append(f"  write_bytes_per_dispatch: {wb:.0f}")
+        out.append(f"  traffic_bytes_per_dispatch: {fb + wb:.0f}")
+    return "\n".join(out) + "\n"
+
+
+def read_traffic(path: str, kernel_name: str):
+    """Traffic per dispatch of ``kernel_name`` from a summary, or None when the
+    summary is missing, lacks the kernel, or was taken on other sources."""
+    if not os.path.exists(path):
+        return None
+    lines = open(path).read().splitlines()
+    src = next((l.split(":", 1)[1].strip() for l in lines if l.startswith("source_sha256:")), None)
+    if src != source_hash():
+        return None
+    for i, l in enumerate(lines):
+        if l.startswith("kernel:") and l.split(":", 1)[1].strip() == kernel_name:
+            for l2 in lines[i + 1:i + 4]:
+                if "traffic_bytes_per_dispatch" in l2:
+                    return float(l2.split(":")[1])
+    return None
+
+
+def main(argv):
+    if argv[0] == "stats":
+        open(argv[2], "w").write(stats_summary(argv[1], " ".join(argv[3:])))
+    elif argv[0] == "traffic":
+        open(argv[3], "w").write(traffic_summary(argv[1], argv[2], argv[4], float(argv[5]), " ".join(argv[6:])))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
