@@ -29,10 +29,11 @@ if ROOT not in sys.path:
 
 import dg_inputs as I  # noqa: E402
 
-PEAKS = {  # MI355X published peaks
+PEAKS = {  # MI355X published peaks (dense)
     "hbm_GBs": 8000.0,
     "fp64_TFs": 78.6,
     "fp32_TFs": 157.3,
+    "bf16_TFs": 2500.0,   # BF16 and FP16 matrix cores
 }
 
 
@@ -43,6 +44,13 @@ def flops_per_element(N: int) -> int:
     Np = (N + 1) * (N + 2) * (N + 3) // 6
     Nfp = (N + 1) * (N + 2) // 2
     return 36 * Np * Np + 48 * Np * Nfp + 240 * Nfp + 66 * Np
+
+
+def contraction_flops_per_element(N: int) -> int:
+    """Flops of the two dense contractions alone (volume and LIFT)."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    return 36 * Np * Np + 48 * Np * Nfp
 
 
 def bytes_per_element(N: int, s: int) -> int:
@@ -103,7 +111,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--k", type=int, default=24, help="cube resolution (K = 6 k^3)")
     ap.add_argument("--order", type=int, default=4)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64",
+                    choices=["fp64", "fp32", "bf16x3", "f16x3", "bf16x2", "f16x2", "bf16", "f16"])
+    ap.add_argument("--also", default="fp32,f16x3,bf16x3",
+                    help="other precisions measured in the same run (comma separated, may be empty)")
     ap.add_argument("--rhs-reps", type=int, default=50)
     ap.add_argument("--variant", default=None, help="kernel variant (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -132,7 +143,8 @@ def main():
         del src, dst
     traffic_file = args.traffic_file or os.path.join(ROOT, "profiles", f"rhs_traffic_k{k}_n{N}.txt")
     results = {}
-    for prec in (args.precision, "fp32" if args.precision == "fp64" else "fp64"):
+    others = [x for x in args.also.split(",") if x and x != args.precision]
+    for prec in [args.precision] + others:
         p, u, mesh = make_problem(dg, k, N, prec)
         if args.variant:
             p.set_variant(args.variant)
@@ -157,19 +169,33 @@ def main():
         t_total = e0.elapsed_time(e1) / 1e3
         dofs = 6 * K * Np
         flops = flops_per_element(N) * K
-        peak = PEAKS["fp64_TFs"] if prec == "fp64" else PEAKS["fp32_TFs"]
+        peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"]}.get(prec, PEAKS["bf16_TFs"])
         achieved = flops / t_rhs / 1e12
         tname = "double" if prec == "fp64" else "float"
-        kname = (f"void dgd::rhs_mfma_kernel<{N}, {tname}, false>(dgd::RhsArgs)" if p.variant == "mfma"
+        mix = {"fp64": 0, "fp32": 0, "bf16": 1, "bf16x2": 2, "bf16x3": 3, "f16": 4, "f16x2": 5, "f16x3": 6}[prec]
+        kname = (f"void dgd::rhs_mfma_kernel<{N}, {tname}, false, {mix}>(dgd::RhsArgs)" if p.variant == "mfma"
                  else f"void dgd::rhs_valu_kernel<{N}, {tname}>(dgd::RhsArgs)")
         traffic = profiling.read_traffic(traffic_file, kname)
+        # Split precisions: the contractions run at the 16-bit matrix-core rate,
+        # so the bound is whichever of HBM bytes and MFMA work is slower.
+        if prec not in ("fp64", "fp32"):
+            nprod = mix if mix <= 3 else mix - 3
+            t_hbm = bytes_per_element(N, s) * K / (PEAKS["hbm_GBs"] * 1e9)
+            t_mma = nprod * contraction_flops_per_element(N) * K / (PEAKS["bf16_TFs"] * 1e12)
+            if t_hbm >= t_mma:
+                bound, achieved, peak, unit = "hbm", bytes_per_element(N, s) * K / t_rhs / 1e9, PEAKS["hbm_GBs"], "GB/s"
+            else:
+                bound, achieved, peak, unit = "mfma", nprod * contraction_flops_per_element(N) * K / t_rhs / 1e12, \
+                    PEAKS["bf16_TFs"], "TFLOP/s"
+        else:
+            bound, unit = ("mfma" if p.variant == "mfma" else "alu"), "TFLOP/s"
         results[prec] = {
             "value": 5 * dofs * args.steps / t_total / 1e9,
             "ms_per_step": 1e3 * t_total / args.steps,
             "rhs_us": 1e6 * t_rhs,
             "rhs_gdofs": dofs / t_rhs / 1e9,
-            "roofline": {"bound": "mfma" if p.variant == "mfma" else "alu", "achieved": achieved, "peak": peak,
-                         "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "roofline": {"bound": bound, "achieved": achieved, "peak": peak,
+                         "unit": unit, "frac": achieved / peak, "traffic": traffic,
                          "kernel": kname,
                          "algorithmic_flops_per_launch": flops,
                          "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K,
@@ -180,7 +206,6 @@ def main():
         del du, res, out
 
     main_r = results[args.precision]
-    other = "fp32" if args.precision == "fp64" else "fp64"
     line = {
         "metric": "GDOF/s per DG RHS eval (Maxwell tets) and % of HBM/MFMA roofline",
         "value": main_r["value"],
@@ -192,7 +217,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32"}.get(args.precision, args.precision + "+f32acc"),
         "data": "synthetic",
         "config": {"workload": f"jittered Kuhn cube {k}^3x6 tets (K={main_r['K']}), N={N} (Np={main_r['Np']}), "
                                f"PEC cavity + noise, upwind, LSERK(5,4) step = 5 RHS + 5 updates",
@@ -200,7 +225,8 @@ def main():
         "roofline": main_r["roofline"],
         "rhs_us": main_r["rhs_us"],
         "rhs_gdofs": main_r["rhs_gdofs"],
-        "other_precision": {other: {kk: results[other][kk] for kk in ("value", "ms_per_step", "rhs_us", "rhs_gdofs", "roofline", "variant")}},
+        "other_precision": {o: {kk: results[o][kk] for kk in ("value", "ms_per_step", "rhs_us", "rhs_gdofs", "roofline",
+                                                             "variant")} for o in others},
     }
     if not args.no_cpu_baseline:
         VX, EToV = I.kuhn_cube(k, 0.1, 0)

@@ -59,8 +59,20 @@ typedef enum {
 
 /* Arithmetic of the right-hand side and of the state arrays.
  *   DG_FP64: state, geometry, operators and all arithmetic in binary64.
- *   DG_FP32: state, geometry, operators and all arithmetic in binary32.     */
-typedef enum { DG_FP64 = 0, DG_FP32 = 1 } dg_precision;
+ *   DG_FP32: state, geometry, operators and all arithmetic in binary32.
+ *   The others keep the state, geometry, fluxes and the Runge-Kutta update
+ *   in binary32 and run the two dense contractions (Dr/Ds/Dt and LIFT) on
+ *   16-bit matrix cores with binary32 accumulation.  Each operand a is split
+ *   as a = a_hi + a_lo, a_hi = round16(a), a_lo = round16(a - a_hi):
+ *   DG_BF16 / DG_F16:      a_hi b_hi                        (one product)
+ *   DG_BF16X2 / DG_F16X2:  a_hi b_hi + a_lo b_hi            (operator split)
+ *   DG_BF16X3 / DG_F16X3:  a_hi b_hi + a_lo b_hi + a_hi b_lo (both split)
+ *   where a is the operator and b the fields or fluxes; BF16 = bfloat16,
+ *   F16 = IEEE binary16.  These have only the "mfma" variant.               */
+typedef enum {
+  DG_FP64 = 0, DG_FP32 = 1, DG_BF16X3 = 2, DG_F16X3 = 3,
+  DG_BF16 = 4, DG_F16 = 5, DG_BF16X2 = 6, DG_F16X2 = 7
+} dg_precision;
 
 typedef struct dg_problem_s* dg_problem;  /* opaque; owns all mesh-derived device data */
 
@@ -88,7 +100,7 @@ typedef struct {
   int64_t K;
   int64_t field_stride;  /* scalars                                               */
   int64_t state_elems;   /* scalars in one state array                            */
-  int32_t elem_bytes;    /* 8 (FP64) or 4 (FP32)                                  */
+  int32_t elem_bytes;    /* 8 (DG_FP64) or 4 (every other precision)              */
   int32_t tile_elems;    /* elements per workgroup of the RHS kernel              */
   double dt_cfl1;        /* 2 / ((N+1)^2 max Fscale): dt at CFL number 1          */
   double alpha;

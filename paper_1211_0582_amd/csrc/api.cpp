@@ -28,6 +28,7 @@ struct dg_problem_s {
   uint8_t* d_nbr = nullptr;
   int32_t* d_fmask = nullptr;
   void* d_frag = nullptr;     // MFMA A-fragments of [Dr|Ds|Dt|LIFT]
+  void* d_frag16 = nullptr;   // the same split into 16-bit heads and tails (split precisions)
   void* d_scratch = nullptr;  // rhs buffer (unfused stepping) / second state buffer (fused)
   std::vector<double> verts;  // K x 4 x 3 vertex coordinates (for dg_nodes)
   int variant = 0;
@@ -43,6 +44,55 @@ const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0
 const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                         2277821191437.0 / 14882151754819.0};
+
+// Round-to-nearest-even conversions to the 16-bit formats (host side).
+uint16_t float_to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t(u >> 16);  // inf / nan (not produced here)
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+float bf16_to_float(uint16_t h) {
+  const uint32_t u = uint32_t(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+uint16_t float_to_f16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t sign = (u >> 16) & 0x8000u;
+  const float a = std::fabs(f);
+  if (a >= 65520.0f) return uint16_t(sign | 0x7c00u);         // overflow -> inf
+  if (a < 5.9604645e-8f * 0.5f) return uint16_t(sign);        // rounds to zero
+  int ex;
+  const double m = std::frexp(double(a), &ex);               // a = m 2^ex, m in [0.5, 1)
+  int e16 = ex - 1 + 15;                                       // biased exponent of 1.x form
+  double q;
+  if (e16 <= 0) {                                              // subnormal: units of 2^-24
+    q = std::nearbyint(double(a) * 16777216.0);
+    return uint16_t(sign | uint32_t(q));                       // q may reach 1024 = smallest normal
+  }
+  q = std::nearbyint((m * 2.0 - 1.0) * 1024.0);                // 10-bit fraction, ties to even
+  if (q >= 1024.0) {
+    q = 0.0;
+    ++e16;
+  }
+  if (e16 >= 31) return uint16_t(sign | 0x7c00u);
+  return uint16_t(sign | (uint32_t(e16) << 10) | uint32_t(q));
+}
+float f16_to_float(uint16_t h) {
+  const uint32_t e = (h >> 10) & 0x1fu, fr = h & 0x3ffu;
+  float v;
+  if (e == 0)
+    v = std::ldexp(float(fr), -24);
+  else if (e == 31)
+    v = fr ? NAN : INFINITY;
+  else
+    v = std::ldexp(float(fr + 1024u), int(e) - 25);
+  return (h & 0x8000u) ? -v : v;
+}
 
 dg_status hip_fail(hipError_t e, const char* what) {
   return fail(e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -67,6 +117,7 @@ void free_problem(dg_problem p) {
   hipFree(p->d_nbr);
   hipFree(p->d_fmask);
   hipFree(p->d_frag);
+  hipFree(p->d_frag16);
   hipFree(p->d_scratch);
   delete p;
 }
@@ -133,6 +184,39 @@ dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
       }
   DG_HIP(hipMalloc(&p->d_frag, frag.size() * sizeof(T)), "hipMalloc(fragments)");
   DG_HIP(hipMemcpy(p->d_frag, frag.data(), frag.size() * sizeof(T), hipMemcpyHostToDevice), "upload fragments");
+
+  // 16x16x16 fragments of the split precisions: row block ib, depth step s,
+  // lane l holds for v = 0..3 the head and tail of Op[16 ib + l % 16][kappa],
+  // kappa = 16 s + 4 (l / 16) + v; depth = 3 volume blocks of Np4 padded to 16,
+  // then LIFT padded to 16.
+  if (p->precision >= DG_BF16X3) {
+    const bool bf = p->precision == DG_BF16X3 || p->precision == DG_BF16 || p->precision == DG_BF16X2;
+    const int KV = (3 * Np4 + 15) / 16 * 16, KL = (NF + 15) / 16 * 16, ST = (KV + KL) / 16;
+    std::vector<uint16_t> f16(size_t(RB) * ST * 64 * 8, 0);
+    for (int ib = 0; ib < RB; ++ib)
+      for (int st = 0; st < ST; ++st)
+        for (int l = 0; l < 64; ++l)
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * ib + (l & 15);
+            const int kap = 16 * st + 4 * (l >> 4) + v;
+            double val = 0.0;
+            if (row < Np) {
+              if (kap < KV) {
+                if (kap < 3 * Np4 && kap % Np4 < Np) val = (*D[kap / Np4])(row, kap % Np4);
+              } else if (kap - KV < NF) {
+                val = re.LIFT(row, kap - KV);
+              }
+            }
+            const uint16_t hi = bf ? float_to_bf16(float(val)) : float_to_f16(float(val));
+            const float hv = bf ? bf16_to_float(hi) : f16_to_float(hi);
+            const uint16_t lo = bf ? float_to_bf16(float(val - double(hv))) : float_to_f16(float(val - double(hv)));
+            const size_t base = ((size_t(ib) * ST + st) * 64 + l) * 8;
+            f16[base + v] = hi;
+            f16[base + 4 + v] = lo;
+          }
+    DG_HIP(hipMalloc(&p->d_frag16, f16.size() * 2), "hipMalloc(16-bit fragments)");
+    DG_HIP(hipMemcpy(p->d_frag16, f16.data(), f16.size() * 2, hipMemcpyHostToDevice), "upload 16-bit fragments");
+  }
   return DG_OK;
 }
 
@@ -144,6 +228,7 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   a.conn = p->d_conn;
   a.ops = p->d_ops;
   a.ops_frag = p->d_frag;
+  a.ops_frag16 = p->d_frag16;
   a.nbr = p->d_nbr;
   a.fmask = p->d_fmask;
   a.K = p->K;
@@ -221,8 +306,7 @@ dg_status dg_host_mesh(int32_t N, int64_t Nv, const double* VX, int64_t K, const
 dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   clear_error();
   if (!desc || !out) return fail(DG_EINVAL, "null argument");
-  if (desc->precision != DG_FP64 && desc->precision != DG_FP32)
-    return fail(DG_EINVAL, "precision must be DG_FP64 or DG_FP32");
+  if (desc->precision < DG_FP64 || desc->precision > DG_F16X2) return fail(DG_EINVAL, "precision out of range");
   if (!std::isfinite(desc->alpha)) return fail(DG_EINVAL, "alpha must be finite");
   if (desc->N < 1 || desc->N > kMaxOrder) return fail(DG_EUNSUPPORTED, "order N must be in 1..9");
   HostMesh hm;
@@ -251,6 +335,10 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   if (!p->ks.rhs) {
     p->variant = dgd::kVariantValu;
     p->ks = dgd::kernels(desc->N, desc->precision, p->variant);
+  }
+  if (!p->ks.rhs) {
+    delete p;
+    return fail(DG_EUNSUPPORTED, "no kernel for this order and precision");
   }
   p->tile = p->ks.tile;
   hipGetDevice(&p->device);

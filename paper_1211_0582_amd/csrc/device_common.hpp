@@ -20,6 +20,7 @@ struct RhsArgs {
   const int32_t* conn;    // K x 4, -1 wall, else nbr*32 + nbr_face*6 + orient
   const void* ops;        // Dr^T, Ds^T, Dt^T (Np x Np each, [j][i]), LIFT^T (4Nfp x Np, [m][i])
   const void* ops_frag;   // [Dr|Ds|Dt|LIFT] as 16x4 MFMA A-fragments [row block][depth step][lane]
+  const void* ops_frag16; // same operator split into 16-bit heads and tails, 16x16x16 A-fragments
   const uint8_t* nbr;     // 4 x 24 x Nfp neighbour volume node per (face, code, j)
   const int32_t* fmask;   // 4 x Nfp
   int64_t K;
@@ -51,9 +52,10 @@ struct KernelSet {
   RhsLauncher rk = nullptr;   // fused Runge-Kutta stage (nullptr: rhs + update kernel)
   int tile = 0;               // elements per workgroup
   int frag_count = 0;         // scalars of the MFMA fragment array (0 if unused)
+  int frag16_bytes = 0;       // bytes of the 16-bit split fragment array (0 if unused)
 };
 
-// Kernels for order N (1..9), precision (0 = FP64, 1 = FP32) and variant;
+// Kernels for order N (1..9), precision (dg_precision) and variant;
 // rhs == nullptr when the combination is not built.
 KernelSet kernels(int N, int precision, int variant);
 

@@ -31,10 +31,37 @@ KernelSet make(int variant) {
   }
   return k;
 }
+
+// Split 16-bit contraction (FP32 state): matrix-core variant only.
+template <int MIX>
+KernelSet make_mixed(int variant) {
+  constexpr int N = DG_ORDER;
+  KernelSet k;
+  if (variant == kVariantMfma) {
+    if constexpr (mfma_supported<N, float>()) {
+      k.rhs = &launch_rhs_mfma<N, float, MIX>;
+      k.rk = &launch_rk_mfma<N, float, MIX>;
+      k.tile = 16;
+      k.frag16_bytes = MixedShape<N>::frag_bytes;
+    }
+  }
+  return k;
+}
 }  // namespace
 
+// precision: 0 FP64, 1 FP32, 2 BF16x3, 3 FP16x3, 4 BF16, 5 FP16, 6 BF16x2, 7 FP16x2
 KernelSet DG_CAT(kernels_n, DG_ORDER)(int precision, int variant) {
-  return precision == 0 ? make<double>(variant) : make<float>(variant);
+  switch (precision) {
+    case 0: return make<double>(variant);
+    case 1: return make<float>(variant);
+    case 2: return make_mixed<3>(variant);
+    case 3: return make_mixed<6>(variant);
+    case 4: return make_mixed<1>(variant);
+    case 5: return make_mixed<4>(variant);
+    case 6: return make_mixed<2>(variant);
+    case 7: return make_mixed<5>(variant);
+    default: return KernelSet{};
+  }
 }
 
 }  // namespace dgd

@@ -26,6 +26,8 @@
 //    contiguous range of elements (neighbours then share that XCD's L2).
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "rhs_valu.hpp"
 
@@ -201,9 +203,168 @@ __device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split-precision contraction on 16-bit matrix cores.
+//
+// Same product as mfma_wave, with 16x16x16 MFMAs in BF16 or FP16 and FP32
+// accumulation.  Both operands are split into a 16-bit head and a 16-bit
+// tail, a = a_hi + a_lo with a_hi = round(a), a_lo = round(a - a_hi); the
+// operator's split is done once on the host, the fields' and fluxes' split in
+// registers.  NPROD selects the products accumulated: 1: a_hi b_hi,
+// 2: + a_lo b_hi, 3: + a_hi b_lo (the a_lo b_lo term is below FP32 rounding).
+// Depth: the volume columns (3 directions x Np4) padded to 16, then the LIFT
+// columns padded to 16; a lane's 4 consecutive depth entries always lie in
+// one direction block or in the LIFT block.
+template <typename H16>
+struct Mfma16x16;
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+template <>
+struct Mfma16x16<__bf16> {
+  using v4 = bf16x4;
+  __device__ static inline f32x4 mac(v4 a, v4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16x16<_Float16> {
+  using v4 = f16x4;
+  __device__ static inline f32x4 mac(v4 a, v4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int N>
+struct MixedShape {
+  using S = MfmaShape<N>;
+  static constexpr int KV = ((3 * S::Np4 + 15) / 16) * 16;  // volume depth, padded
+  static constexpr int KL = ((S::NF + 15) / 16) * 16;       // LIFT depth, padded
+  static constexpr int SV = KV / 16, SL = KL / 16, ST = SV + SL;
+  // fragments: [row block][depth step][lane] x (4 heads, 4 tails) of 16 bits
+  static constexpr int frag_bytes = S::RB * ST * 64 * 16;
+};
+
+template <typename H16>
+__device__ inline void split4(const float (&x)[4], typename Mfma16x16<H16>::v4& hi,
+                              typename Mfma16x16<H16>::v4& lo) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const H16 h = static_cast<H16>(x[v]);
+    hi[v] = h;
+    lo[v] = static_cast<H16>(x[v] - static_cast<float>(h));
+  }
+}
+
+template <int N, typename H16, int NPROD, int H, typename FluxPhase>
+__device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane,
+                                  int64_t k0, f32x4 (&acc)[MfmaShape<N>::RB][3], FluxPhase&& flux_phase) {
+  using S = MfmaShape<N>;
+  using X = MixedShape<N>;
+  using MM = Mfma16x16<H16>;
+  using v4 = typename MM::v4;
+  constexpr int Np4 = S::Np4, NF = S::NF, RB = S::RB, TS = S::TS;
+  constexpr int SV = X::SV, SL = X::SL, ST = X::ST;
+  const int e = lane & 15, q = lane >> 4;
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag16, uint32_t(X::frag_bytes));
+#pragma unroll
+  for (int ib = 0; ib < RB; ++ib)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[ib][c] = f32x4{0, 0, 0, 0};
+
+  // A fragments (head, tail) prefetched kPre steps ahead.
+  constexpr int kPre = 2;
+  auto frag_of = [&](int step, int ib, v4& hi, v4& lo) {
+    const uint32_t off = uint32_t(((ib * ST + step) * 64 + lane) * 16);
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 0, 0);
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    hi = __builtin_bit_cast(v4, u32x2{w[0], w[1]});
+    lo = __builtin_bit_cast(v4, u32x2{w[2], w[3]});
+  };
+  v4 Ahi[kPre + 1][RB], Alo[kPre + 1][RB];
+#pragma unroll
+  for (int s = 0; s < kPre; ++s)
+#pragma unroll
+    for (int ib = 0; ib < RB; ++ib) frag_of(s, ib, Ahi[s][ib], Alo[s][ib]);
+
+  auto mma = [&](int step, const v4 (&bh)[3], const v4 (&bl)[3]) {
+    const int slot = step % (kPre + 1);
+#pragma unroll
+    for (int ib = 0; ib < RB; ++ib)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[ib][c] = MM::mac(Ahi[slot][ib], bh[c], acc[ib][c]);
+        if constexpr (NPROD >= 2) acc[ib][c] = MM::mac(Alo[slot][ib], bh[c], acc[ib][c]);
+        if constexpr (NPROD >= 3) acc[ib][c] = MM::mac(Ahi[slot][ib], bl[c], acc[ib][c]);
+      }
+  };
+
+  // Volume: depth entries kappa = 16 s + 4 q + v, direction d = kappa / Np4,
+  // node j = kappa % Np4; operand X_d = m_d x V with V = H (H = 0) or -E.
+  constexpr int vb = H ? 0 : 3;
+  const float vs = H ? -1.f : 1.f;
+#pragma unroll
+  for (int s = 0; s < SV; ++s) {
+    if (s + kPre < ST) {
+#pragma unroll
+      for (int ib = 0; ib < RB; ++ib) frag_of(s + kPre, ib, Ahi[(s + kPre) % (kPre + 1)][ib], Alo[(s + kPre) % (kPre + 1)][ib]);
+    }
+    const int kap = 16 * s + 4 * q;
+    float xv[3][4];
+    if (kap < 3 * Np4) {
+      const int d = kap / Np4, j = kap - d * Np4;
+      const float mx = mr[3 * d], my = mr[3 * d + 1], mz = mr[3 * d + 2];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float v0 = vs * t.su[((vb + 0) * Np4 + j + v) * TS + e];
+        const float v1 = vs * t.su[((vb + 1) * Np4 + j + v) * TS + e];
+        const float v2 = vs * t.su[((vb + 2) * Np4 + j + v) * TS + e];
+        xv[0][v] = my * v2 - mz * v1;
+        xv[1][v] = mz * v0 - mx * v2;
+        xv[2][v] = mx * v1 - my * v0;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xv[c][v] = 0.f;
+    }
+    v4 bh[3], bl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) split4<H16>(xv[c], bh[c], bl[c]);
+    mma(s, bh, bl);
+  }
+
+  // Lifting: fluxes from the LDS flux tile written by the workgroup.
+  flux_phase(t, k0);
+  __syncthreads();
+  constexpr int cb = H ? 3 : 0;
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int step = SV + s;
+    if (step + kPre < ST) {
+#pragma unroll
+      for (int ib = 0; ib < RB; ++ib)
+        frag_of(step + kPre, ib, Ahi[(step + kPre) % (kPre + 1)][ib], Alo[(step + kPre) % (kPre + 1)][ib]);
+    }
+    const int m = 16 * s + 4 * q;
+    float fv[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) fv[c][v] = (m + v < NF) ? t.su[((cb + c) * NF + m + v) * TS + e] : 0.f;
+    v4 bh[3], bl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) split4<H16>(fv[c], bh[c], bl[c]);
+    mma(step, bh, bl);
+  }
+}
+
 // Workgroup = two waves sharing one tile of 16 elements; wave h = 0 produces
 // the E equations, wave h = 1 the H equations (see mfma_wave).
-template <int N, typename T, bool RK>
+// MIX = 0: contraction in T on 16x16x4 MFMAs; MIX = 1..3: T = float with the
+// contraction split in BF16 (NPROD = MIX); MIX = 4..6: split in FP16
+// (NPROD = MIX - 3).
+template <int N, typename T, bool RK, int MIX>
 __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
@@ -363,10 +524,19 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
   };
 
   acc_t acc[RB][3];
-  if (h == 0)
-    mfma_wave<N, T, 0>(a, t, mr, lane, k0, acc, flux_phase);
-  else
-    mfma_wave<N, T, 1>(a, t, mr, lane, k0, acc, flux_phase);
+  if constexpr (MIX == 0) {
+    if (h == 0)
+      mfma_wave<N, T, 0>(a, t, mr, lane, k0, acc, flux_phase);
+    else
+      mfma_wave<N, T, 1>(a, t, mr, lane, k0, acc, flux_phase);
+  } else {
+    using H16 = typename std::conditional<(MIX <= 3), __bf16, _Float16>::type;
+    constexpr int NPROD = MIX <= 3 ? MIX : MIX - 3;
+    if (h == 0)
+      mixed_wave<N, H16, NPROD, 0>(a, t, mr, lane, k0, acc, flux_phase);
+    else
+      mixed_wave<N, H16, NPROD, 1>(a, t, mr, lane, k0, acc, flux_phase);
+  }
 
   // Epilogue through LDS: [c][e][i] for this wave's three fields, then
   // contiguous stores per field.
@@ -423,19 +593,19 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
   }
 }
 
-template <int N, typename T>
+template <int N, typename T, int MIX = 0>
 hipError_t launch_rhs_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false>), dim3(grid), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false, MIX>), dim3(grid), dim3(128), 0, s, a);
   return hipGetLastError();
 }
 
-template <int N, typename T>
+template <int N, typename T, int MIX = 0>
 hipError_t launch_rk_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true>), dim3(grid), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true, MIX>), dim3(grid), dim3(128), 0, s, a);
   return hipGetLastError();
 }
 

@@ -16,8 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_EINVAL, DG_EMESH, DG_EHIP, DG_ENOMEM, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-DG_FP64, DG_FP32 = 0, 1
-PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32}
+DG_FP64, DG_FP32, DG_BF16X3, DG_F16X3, DG_BF16, DG_F16, DG_BF16X2, DG_F16X2 = range(8)
+PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16x3": DG_BF16X3, "f16x3": DG_F16X3, "bf16": DG_BF16,
+              "f16": DG_F16, "bf16x2": DG_BF16X2, "f16x2": DG_F16X2}
 
 #: every symbol the public headers declare
 EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",

@@ -255,3 +255,54 @@ def test_config2_fused_stage_matches_rhs_plus_update(dg, variant):
     p.close()
     _say(f"  rel err {err:.3e}")
     assert err < 1e-12
+
+
+# Split 16-bit contractions: error against the FP64 oracle, stated per
+# precision (relative to max |rhs|).  The volume and lift terms are each
+# larger than their sum by about the metric scale times N^2, so a relative
+# rounding u of the B operand (fields, fluxes) shows up magnified in the
+# result: heads alone (x1) and an operator-only split (x2) leave the operand
+# rounding (BF16 u = 2^-9, FP16 u = 2^-12) in place; splitting the operand too
+# (x3) leaves u^2-level terms plus FP32 accumulation.  Measured on MI355X at
+# k = 2..3, N = 2..7 (worst over N, divided by max(1, N/4)): bf16 0.16,
+# bf16x2 0.16, bf16x3 2.8e-4, f16 1.6e-2, f16x2 1.3e-2, f16x3 4.9e-6; at the
+# full K = 82,944 mesh bf16x3 9.4e-4, f16x3 2.2e-5.  Bounds: about 3x those.
+SPLIT_TOL = {"bf16": 5e-1, "bf16x2": 5e-1, "bf16x3": 1e-3, "f16": 5e-2, "f16x2": 5e-2, "f16x3": 2e-5}
+SPLIT_TOL_FULL = {"bf16x3": 3e-3, "f16x3": 7e-5}
+
+
+@pytest.mark.parametrize("precision", list(SPLIT_TOL))
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7])
+def test_split_precision_rhs(dg, N, precision):
+    k = 3 if N <= 5 else 2
+    _say(f"[gpu] split rhs N={N} {precision}")
+    VX, EToV, m, u, ref = _case(N, k)
+    got = _gpu_rhs(dg, N, VX, EToV, u, precision, "mfma")
+    err = _rel(got, ref)
+    _say(f"  {precision} N={N} rel err {err:.3e}")
+    assert err < SPLIT_TOL[precision] * max(1.0, N / 4)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3"])
+def test_split_precision_full_size_and_steps(dg, precision):
+    import torch
+    _say(f"[gpu] split precision full size {precision}")
+    VX, EToV, m, u, ref = _case(4, 24)
+    got = _gpu_rhs(dg, 4, VX, EToV, u, precision, "mfma")
+    err = _rel(got, ref)
+    _say(f"  {precision} K=82944 rel err {err:.3e}")
+    assert err < SPLIT_TOL_FULL[precision]
+    VX, EToV = I.kuhn_cube(3, 0.1, 0)
+    mm = Me.Mesh(4, VX, EToV)
+    u0 = I.cavity_mode(mm.x, mm.y, mm.z)
+    dt = D.dt_cfl(mm, 0.5)
+    ref = L.integrate(lambda v, t: Mx.rhs(mm, v), u0, 0.0, dt, 20)
+    p = _problem(dg, 4, VX, EToV, precision, "mfma")
+    du = p.pack(u0)
+    res = p.zeros_state()
+    p.rk_step(du, res, 0.0, dt, 20)
+    torch.cuda.synchronize()
+    err = _rel(p.unpack(du), ref)
+    p.close()
+    _say(f"  {precision} 20 LSERK steps rel err {err:.3e}")
+    assert err < SPLIT_TOL[precision]

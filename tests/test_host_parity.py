@@ -90,7 +90,7 @@ def test_setup_rejects_bad_input_before_device_work():
     assert e.value.status == dg.DG_EMESH
     # setup validates the same way (and the precision enum) before touching a GPU
     with pytest.raises(dg.DgError) as e:
-        dg.dg_setup_mesh(2, VX, EToV, precision=7)
+        dg.dg_setup_mesh(2, VX, EToV, precision=99)
     assert e.value.status == dg.DG_EINVAL
     with pytest.raises(dg.DgError) as e:
         dg.dg_setup_mesh(0, VX, EToV)
