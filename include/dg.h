@@ -149,6 +149,39 @@ dg_status dg_set_variant(dg_problem p, int32_t v);
 dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
                      int32_t nsteps, void* stream);
 
+/* ---- Batches of independent problems -------------------------------------
+ * A batch owns n problems (any mix of orders and sizes, one precision) and
+ * steps them together: problems are grouped by order N and each Runge-Kutta
+ * stage is one launch per group over all of its (problem, element tile)
+ * pairs.  The paper notes that the host's launch rate only suffices when each
+ * launch carries enough work; batching many small problems restores that. */
+typedef struct dg_batch_s* dg_batch;
+
+/* Sets up descs[0..n-1] (host array) as one batch.  All problems must share
+ * one precision and have a batched kernel (the "mfma" variant is built for
+ * their order and precision).  Errors: as dg_setup_mesh (the message names
+ * the problem), DG_EINVAL (n < 1, mixed precisions). */
+dg_status dg_setup_batch(int32_t n, const dg_mesh_desc* descs, dg_batch* out);
+
+/* Borrowed handle of problem i (for dg_info_get, dg_pack, dg_unpack,
+ * dg_nodes, dg_rhs); it stays owned by the batch: never dg_destroy it. */
+dg_status dg_batch_problem(dg_batch b, int32_t i, dg_problem* p);
+
+/* nsteps LSERK steps of every problem, in place.  u, res, dt: host arrays of
+ * n device pointers / time steps; u[i], res[i] are state arrays of problem
+ * i.  mode 0: each step replays a graph of (5 stages x order groups) kernel
+ * launches, captured on the first call; mode 1: the same launches issued
+ * directly; mode 2: one launch per problem and stage (dg_rk_step per
+ * problem).  All modes give bitwise identical results.  Asynchronous on
+ * stream; the descriptor upload (when pointers or dt change) is staged
+ * before the call returns.  Errors: DG_EINVAL (null or aliasing pointers,
+ * nsteps < 0, dt not finite, mode), DG_EHIP. */
+dg_status dg_rk_step_batch(dg_batch b, void* const* u, void* const* res, const double* dt,
+                           int32_t nsteps, int32_t mode, void* stream);
+
+/* Releases the batch and its problems; NULL is a no-op. */
+void dg_destroy_batch(dg_batch b);
+
 /* Host <-> device conversion between the canonical host layout
  * [6][K][Np] binary64 (host pointer) and a device state array (layout above,
  * problem precision).  dg_pack zeroes the padding.  Both block until the copy

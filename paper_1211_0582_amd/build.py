@@ -37,7 +37,7 @@ def _jobs():
     for name in ("host_refelem.cpp", "host_mesh.cpp"):
         src = os.path.join(CSRC, name)
         jobs.append(([CXX, *HOST_FLAGS, "-c", src, "-o", os.path.join(BUILD, name + ".o")], name))
-    for name in ("api.cpp", "lserk.hip"):
+    for name in ("api.cpp", "batch.cpp", "lserk.hip"):
         src = os.path.join(CSRC, name)
         lang = ["-x", "hip"] if name.endswith(".cpp") else []
         jobs.append(([HIPCC, *HIP_FLAGS, *lang, "-c", src, "-o", os.path.join(BUILD, name + ".o")], name))

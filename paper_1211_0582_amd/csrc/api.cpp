@@ -15,35 +15,25 @@
 #include "dg_host.h"
 #include "device_common.hpp"
 #include "host_common.hpp"
+#include "problem.hpp"
 
 using namespace dgh;
 
-struct dg_problem_s {
-  int N = 0, Np = 0, Nfp = 0, precision = 0, elem_bytes = 8, tile = 1, device = 0;
-  int64_t K = 0, fs = 0, state_elems = 0, n_boundary = 0;
-  double alpha = 1.0, dt_cfl1 = 0.0;
-  void* d_geo = nullptr;
-  int32_t* d_conn = nullptr;
-  void* d_ops = nullptr;
-  uint8_t* d_nbr = nullptr;
-  int32_t* d_fmask = nullptr;
-  void* d_frag = nullptr;     // MFMA A-fragments of [Dr|Ds|Dt|LIFT]
-  void* d_frag16 = nullptr;   // the same split into 16-bit heads and tails (split precisions)
-  void* d_scratch = nullptr;  // rhs buffer (unfused stepping) / second state buffer (fused)
-  std::vector<double> verts;  // K x 4 x 3 vertex coordinates (for dg_nodes)
-  int variant = 0;
-  dgd::KernelSet ks;
-};
+
 
 namespace {
 
 // Coefficients of the five-stage, fourth-order 2N-storage Runge-Kutta scheme
 // of Carpenter and Kennedy (1994).
+}  // namespace
+
 const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
                         -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
 const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                         2277821191437.0 / 14882151754819.0};
+
+namespace {
 
 // Round-to-nearest-even conversions to the 16-bit formats (host side).
 uint16_t float_to_bf16(float f) {
@@ -220,6 +210,8 @@ dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
   return DG_OK;
 }
 
+}  // namespace
+
 dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   dgd::RhsArgs a;
   a.u = u;
@@ -240,8 +232,8 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   return a;
 }
 
+namespace {
 const char* const kVariantNames[dgd::kVariantCount] = {"valu", "mfma"};
-
 }  // namespace
 
 extern "C" {

@@ -32,6 +32,31 @@ struct RhsArgs {
   double rk_a, rk_b, rk_dt;
 };
 
+// One problem of a batch (device descriptor table entry).
+struct BatchProblem {
+  void* u;               // caller's state
+  void* res;             // caller's residual
+  void* u2;              // library-owned second state buffer
+  const void* geo;
+  const int32_t* conn;
+  int64_t K, fs;
+  double dt, alpha;
+};
+
+// One batched Runge-Kutta stage over the problems of one order N.
+struct BatchArgs {
+  const BatchProblem* probs;
+  const int2* items;      // (problem, tile) pairs
+  int64_t n_items;
+  const void* ops_frag;   // operator fragments of order N (shared by the group)
+  const void* ops_frag16;
+  const uint8_t* nbr;
+  const int32_t* fmask;
+  int parity;
+  double rk_a, rk_b;
+};
+using BatchLauncher = hipError_t (*)(const BatchArgs&, hipStream_t);
+
 // Arguments of one LSERK stage update: res <- a res + dt rhs; u <- u + b res.
 struct UpdateArgs {
   void* u;
@@ -53,6 +78,7 @@ struct KernelSet {
   int tile = 0;               // elements per workgroup
   int frag_count = 0;         // scalars of the MFMA fragment array (0 if unused)
   int frag16_bytes = 0;       // bytes of the 16-bit split fragment array (0 if unused)
+  BatchLauncher batch = nullptr;  // batched fused stage (matrix-core variant)
 };
 
 // Kernels for order N (1..9), precision (dg_precision) and variant;

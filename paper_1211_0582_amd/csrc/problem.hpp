@@ -1,0 +1,33 @@
+// Internal definition of a problem handle, shared by the C ABI sources.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "dg.h"
+#include "device_common.hpp"
+
+struct dg_problem_s {
+  int N = 0, Np = 0, Nfp = 0, precision = 0, elem_bytes = 8, tile = 1, device = 0;
+  int64_t K = 0, fs = 0, state_elems = 0, n_boundary = 0;
+  double alpha = 1.0, dt_cfl1 = 0.0;
+  void* d_geo = nullptr;
+  int32_t* d_conn = nullptr;
+  void* d_ops = nullptr;
+  uint8_t* d_nbr = nullptr;
+  int32_t* d_fmask = nullptr;
+  void* d_frag = nullptr;     // MFMA A-fragments of [Dr|Ds|Dt|LIFT]
+  void* d_frag16 = nullptr;   // the same split into 16-bit heads and tails (split precisions)
+  void* d_scratch = nullptr;  // rhs buffer (unfused stepping) / second state buffer (fused)
+  std::vector<double> verts;  // K x 4 x 3 vertex coordinates (for dg_nodes)
+  int variant = 0;
+  dgd::KernelSet ks;
+};
+
+// Coefficients of the five-stage, fourth-order 2N-storage Runge-Kutta scheme
+// of Carpenter and Kennedy (1994).
+extern const double kRkA[5];
+extern const double kRkB[5];
+
+// Kernel arguments of a right-hand-side evaluation of p.
+dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs);

@@ -25,6 +25,7 @@ KernelSet make(int variant) {
     if constexpr (mfma_supported<N, T>()) {
       k.rhs = &launch_rhs_mfma<N, T>;
       k.rk = &launch_rk_mfma<N, T>;
+      k.batch = &launch_rk_mfma_batch<N, T>;
       k.tile = 16;
       k.frag_count = MfmaShape<N>::frag_count;
     }

@@ -365,7 +365,7 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
 // contraction split in BF16 (NPROD = MIX); MIX = 4..6: split in FP16
 // (NPROD = MIX - 3).
 template <int N, typename T, bool RK, int MIX>
-__global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
+__device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
@@ -377,12 +377,6 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
   const int lane = tid & 63;
   const int h = tid >> 6;
   const int e = lane & 15, q = lane >> 4;
-
-  // XCD-aware tile: workgroup b runs on XCD b % 8; give each XCD a contiguous range.
-  const int64_t nt = (a.K + 15) / 16;
-  const int64_t per = (nt + 7) / 8;
-  const int64_t tile = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (tile >= nt) return;
   const int64_t k0 = tile * 16;
   const int ne = int((a.K - k0) < 16 ? (a.K - k0) : 16);
   const bool live = e < ne;
@@ -591,6 +585,58 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
       }
     }
   }
+}
+
+// Workgroup b runs on XCD b % 8; give each XCD a contiguous range of the
+// n tiles (launch 8 * ceil(n / 8) workgroups; the surplus returns).
+__device__ inline int64_t xcd_tile(int64_t n) {
+  const int64_t per = (n + 7) / 8;
+  return int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <int N, typename T, bool RK, int MIX>
+__global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
+  const int64_t tile = xcd_tile((a.K + 15) / 16);
+  if (tile >= (a.K + 15) / 16) return;
+  rhs_mfma_tile<N, T, RK, MIX>(a, tile);
+}
+
+// One Runge-Kutta stage for every problem of a batch that has order N: the
+// work list holds (problem, tile) pairs, problem by problem; per-problem
+// pointers come from the descriptor table.  parity 0 reads u and writes the
+// second state buffer, parity 1 the reverse.
+template <int N, typename T, int MIX>
+__global__ __launch_bounds__(128) void rk_mfma_batch_kernel(BatchArgs b) {
+  const int64_t item = xcd_tile(b.n_items);
+  if (item >= b.n_items) return;
+  const int2 w = b.items[item];
+  const BatchProblem& P = b.probs[w.x];
+  RhsArgs a;
+  a.u = b.parity ? P.u2 : P.u;
+  a.u_out = b.parity ? P.u : P.u2;
+  a.res = P.res;
+  a.rhs = nullptr;
+  a.geo = P.geo;
+  a.conn = P.conn;
+  a.ops = nullptr;
+  a.ops_frag = b.ops_frag;
+  a.ops_frag16 = b.ops_frag16;
+  a.nbr = b.nbr;
+  a.fmask = b.fmask;
+  a.K = P.K;
+  a.fs = P.fs;
+  a.alpha = P.alpha;
+  a.rk_a = b.rk_a;
+  a.rk_b = b.rk_b;
+  a.rk_dt = P.dt;
+  rhs_mfma_tile<N, T, true, MIX>(a, w.y);
+}
+
+template <int N, typename T, int MIX = 0>
+hipError_t launch_rk_mfma_batch(const BatchArgs& b, hipStream_t s) {
+  const unsigned grid = unsigned(8 * ((b.n_items + 7) / 8));
+  hipLaunchKernelGGL((rk_mfma_batch_kernel<N, T, MIX>), dim3(grid), dim3(128), 0, s, b);
+  return hipGetLastError();
 }
 
 template <int N, typename T, int MIX = 0>

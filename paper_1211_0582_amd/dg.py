@@ -23,6 +23,7 @@ PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16x3": DG_BF16X3, "f16x3": DG
 #: every symbol the public headers declare
 EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",
             "dg_destroy", "dg_last_error", "dg_variant_count", "dg_variant_name", "dg_set_variant",
+            "dg_setup_batch", "dg_batch_problem", "dg_rk_step_batch", "dg_destroy_batch",
             "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
 
 
@@ -67,6 +68,10 @@ def _load():
         "dg_variant_count": (C.c_int32, []),
         "dg_variant_name": (C.c_char_p, [C.c_int32]),
         "dg_set_variant": (C.c_int, [P, C.c_int32]),
+        "dg_setup_batch": (C.c_int, [C.c_int32, C.POINTER(MeshDesc), C.POINTER(P)]),
+        "dg_batch_problem": (C.c_int, [P, C.c_int32, C.POINTER(P)]),
+        "dg_rk_step_batch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double), C.c_int32, C.c_int32, P]),
+        "dg_destroy_batch": (None, [P]),
         "dg_host_ref_nodes": (C.c_int, [C.c_int32, P, P, P]),
         "dg_host_ref_operators": (C.c_int, [C.c_int32, P, P, P, P, P, P]),
         "dg_host_mesh": (C.c_int, [C.c_int32, C.c_int64, P, C.c_int64, P, P, P, P, P, P, P]),
@@ -281,6 +286,72 @@ class Problem:
         if self.handle:
             dg_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+BATCH_MODES = {"graph": 0, "grouped": 1, "per_problem": 2}
+
+
+class _Borrowed(Problem):
+    """Problem handle owned by a batch (never destroyed by itself)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.info = dg_info_get(handle)
+
+    def close(self):
+        self.handle = None
+
+
+class Batch:
+    """n independent problems stepped together (dg_setup_batch)."""
+
+    def __init__(self, meshes, precision="fp32", alpha=1.0):
+        """meshes: list of (N, VX, EToV)."""
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        keep = []
+        descs = (MeshDesc * len(meshes))()
+        for i, (N, VX, EToV) in enumerate(meshes):
+            VX = np.ascontiguousarray(VX, dtype=np.float64)
+            EToV = np.ascontiguousarray(EToV, dtype=np.int32)
+            keep += [VX, EToV]
+            descs[i] = MeshDesc(N, precision, alpha, VX.shape[0], VX.ctypes.data_as(C.POINTER(C.c_double)),
+                                EToV.shape[0], EToV.ctypes.data_as(C.POINTER(C.c_int32)))
+        h = C.c_void_p()
+        _check(lib.dg_setup_batch(len(meshes), descs, C.byref(h)))
+        self.handle = h
+        self.problems = []
+        for i in range(len(meshes)):
+            ph = C.c_void_p()
+            _check(lib.dg_batch_problem(h, i, C.byref(ph)))
+            self.problems.append(_Borrowed(ph))
+
+    def rk_step(self, us, ress, dts, nsteps=1, mode="graph", stream=None):
+        n = len(self.problems)
+        if not (len(us) == len(ress) == len(dts) == n):
+            raise ValueError(f"need {n} state arrays, residuals and time steps")
+        for p, u, r in zip(self.problems, us, ress):
+            p.check_state(u, "u")
+            p.check_state(r, "res")
+        U = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+        R = (C.c_void_p * n)(*[r.data_ptr() for r in ress])
+        Dt = (C.c_double * n)(*[float(d) for d in dts])
+        _check(lib.dg_rk_step_batch(self.handle, U, R, Dt, int(nsteps), BATCH_MODES.get(mode, mode), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib.dg_destroy_batch(self.handle)
+            self.handle = None
+            self.problems = []
 
     def __del__(self):
         try:

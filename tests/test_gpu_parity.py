@@ -306,3 +306,51 @@ def test_split_precision_full_size_and_steps(dg, precision):
     p.close()
     _say(f"  {precision} 20 LSERK steps rel err {err:.3e}")
     assert err < SPLIT_TOL[precision]
+
+
+# ---------------------------------------------------------------------------
+# Batches: many independent problems of different order and size stepped
+# together.  The grouped launches (with and without graph replay) run the
+# same per-tile code as one launch per problem, so the results are bitwise
+# equal; one problem is also checked against the oracle.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_modes_agree_bitwise_and_match_oracle(dg, precision):
+    import torch
+    _say(f"[gpu] batch modes {precision}")
+    specs = [(2, 3, 11), (4, 2, 12), (3, 4, 13), (4, 1, 14), (5, 2, 15), (2, 1, 16)]
+    if precision == "fp64":
+        specs = [s for s in specs if s[0] <= 4]
+    meshes, oracle_meshes, us = [], [], []
+    for N, k, seed in specs:
+        VX, EToV = I.kuhn_cube(k, 0.1, seed)
+        m = Me.Mesh(N, VX, EToV)
+        meshes.append((N, VX, EToV))
+        oracle_meshes.append(m)
+        us.append(I.cavity_mode(m.x, m.y, m.z) + I.field_noise((6, m.K, m.Np), 1e-3, seed))
+    dts = [D.dt_cfl(m, 0.5) for m in oracle_meshes]
+    results = {}
+    for mode in ("graph", "grouped", "per_problem"):
+        b = dg.Batch(meshes, precision)
+        du = [p.pack(u) for p, u in zip(b.problems, us)]
+        res = [p.zeros_state() for p in b.problems]
+        b.rk_step(du, res, dts, 3, mode)
+        b.rk_step(du, res, dts, 2, mode)     # second call: replays the captured graphs
+        torch.cuda.synchronize()
+        results[mode] = [p.unpack(x) for p, x in zip(b.problems, du)]
+        b.close()
+    for i in range(len(specs)):
+        assert np.array_equal(results["graph"][i], results["per_problem"][i])
+        assert np.array_equal(results["grouped"][i], results["per_problem"][i])
+    m = oracle_meshes[1]
+    ref = L.integrate(lambda v, t: Mx.rhs(m, v), us[1], 0.0, dts[1], 5)
+    err = _rel(results["graph"][1], ref)
+    _say(f"  batch problem 1 vs oracle after 5 steps: {err:.3e}")
+    assert err < (1e-10 if precision == "fp64" else 1e-5)
+
+
+def test_batch_rejects_mixed_precision_and_unsupported(dg):
+    VX, EToV = I.kuhn_cube(1, 0.0, 0)
+    descs = (dg.MeshDesc * 2)()
+    with pytest.raises(dg.DgError):
+        dg.Batch([(3, VX, EToV), (9, VX, EToV)], "fp64")   # FP64 N = 9 has no matrix-core kernel
