@@ -104,6 +104,74 @@ def cpu_baseline(VX, EToV, N, budget_s=20.0):
                       f"(mean {t:.2f} s each); host has {os.cpu_count()} logical CPUs"}
 
 
+def roofline(prec, N, K, t_rhs, s):
+    """(bound, achieved, peak, unit) of one RHS of K elements taking t_rhs s."""
+    flops = flops_per_element(N) * K
+    if prec in ("fp64", "fp32"):
+        peak = PEAKS["fp64_TFs"] if prec == "fp64" else PEAKS["fp32_TFs"]
+        return "mfma", flops / t_rhs / 1e12, peak, "TFLOP/s"
+    nprod = int(prec[-1]) if prec[-1].isdigit() else 1
+    t_hbm = bytes_per_element(N, s) * K / (PEAKS["hbm_GBs"] * 1e9)
+    t_mma = nprod * contraction_flops_per_element(N) * K / (PEAKS["bf16_TFs"] * 1e12)
+    if t_hbm >= t_mma:
+        return "hbm", bytes_per_element(N, s) * K / t_rhs / 1e9, PEAKS["hbm_GBs"], "GB/s"
+    return "mfma", nprod * contraction_flops_per_element(N) * K / t_rhs / 1e12, PEAKS["bf16_TFs"], "TFLOP/s"
+
+
+def bench_sweep(args, torch, dg):
+    """Order sweep: for each N the cube mesh with about 1e7 nodal values per
+    field (k = round((1e7 / (6 Np))^(1/3))), one RHS timed per precision and
+    kernel variant; split precisions report their error against the FP64
+    path on the same fields."""
+    rows = []
+    for N in [int(x) for x in args.sweep_orders.split(",")]:
+        k = I.k_for_dofs(N)
+        VX, EToV = I.kuhn_cube(k, 0.1, 0)
+        ref = None
+        for prec in args.sweep_precisions.split(","):
+            try:
+                p = dg.Problem(N, VX, EToV, prec)
+            except dg.DgError as e:
+                if e.status == dg.DG_EUNSUPPORTED:
+                    continue
+                raise
+            xyz = p.nodes()
+            u = I.cavity_mode(xyz[..., 0], xyz[..., 1], xyz[..., 2]) + I.field_noise((6, p.info.K, p.info.Np), 1e-3, 1)
+            du = p.pack(u)
+            out = p.zeros_state()
+            for v in range(dg.dg_variant_count()):
+                try:
+                    p.set_variant(v)
+                except dg.DgError:
+                    continue
+                t = dg.dg_time_rhs(p.handle, du, out, 3, args.rhs_reps) / 1e3
+                bound, ach, peak, unit = roofline(prec, N, p.info.K, t, p.info.elem_bytes)
+                row = {"N": N, "K": p.info.K, "precision": prec, "variant": p.variant, "rhs_us": 1e6 * t,
+                       "gdofs": 6 * p.info.K * p.info.Np / t / 1e9, "bound": bound, "achieved": ach,
+                       "unit": unit, "frac": ach / peak}
+                if prec == "fp64" and ref is None:
+                    p.rhs(du, out)
+                    torch.cuda.synchronize()
+                    ref = p.unpack(out)
+                if prec != "fp64" and ref is not None:
+                    p.rhs(du, out)
+                    torch.cuda.synchronize()
+                    row["rel_err_vs_fp64"] = float(np.abs(p.unpack(out) - ref).max() / np.abs(ref).max())
+                rows.append(row)
+                print(json.dumps(row), file=sys.stderr, flush=True)
+            p.close()
+            del du, out
+    best = {}
+    for r in rows:
+        key = (r["N"], r["precision"])
+        if key not in best or r["rhs_us"] < best[key]["rhs_us"]:
+            best[key] = r
+    line = {"metric": "GDOF/s per DG RHS eval (Maxwell tets) and % of HBM/MFMA roofline",
+            "workload": "order sweep, about 1e7 nodal values per field per order", "rows": rows,
+            "best": [best[k] for k in sorted(best)]}
+    print(json.dumps(line), flush=True)
+
+
 def bench_batch(args, torch, dg):
     """64 independent cavity problems (k ~ U{4..20}, N ~ U{2..7}, FP32) stepped
     together: graph-replayed grouped launches vs one launch per problem."""
@@ -167,8 +235,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one torch copy of 256 MiB (scale for the HBM traffic counters)")
-    ap.add_argument("--workload", default="single", choices=["single", "batch"],
-                    help="single: one mesh (default); batch: 64 independent problems stepped together")
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "sweep"],
+                    help="single: one mesh (default); batch: 64 independent problems stepped together; "
+                         "sweep: orders 1..9 at about 1e7 nodal values per field")
+    ap.add_argument("--sweep-precisions", default="fp64,fp32,f16x3,bf16x3")
+    ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8,9")
     ap.add_argument("--traffic-file", default=None,
                     help="traffic summary written from rocprofv3 --pmc runs (default: profiles/rhs_traffic_k<k>_n<N>.txt)")
     args = ap.parse_args()
@@ -185,6 +256,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         return bench_batch(args, torch, dg)
+    if args.workload == "sweep":
+        return bench_sweep(args, torch, dg)
     N, k = args.order, args.k
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

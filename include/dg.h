@@ -139,6 +139,14 @@ int32_t dg_variant_count(void);
 const char* dg_variant_name(int32_t v);
 dg_status dg_set_variant(dg_problem p, int32_t v);
 
+/* Timing core of the autotuner (the paper's automated tuning, Section 4):
+ * runs dg_rhs(p, u, rhs) `warmup` times, then `reps` times between two HIP
+ * events on stream, waits for the second event and stores the mean time of
+ * one evaluation in *ms.  Synchronous.  Errors: DG_EINVAL (null pointers,
+ * reps < 1, warmup < 0), DG_EHIP. */
+dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, int32_t reps,
+                      void* stream, double* ms);
+
 /* nsteps steps of the 5-stage low-storage RK4 scheme, in place:
  *   for each stage s: res <- A_s res + dt du/dt(u);  u <- u + B_s res,
  * A_1 = 0, so res needs no initial value.  u, res: device state arrays.

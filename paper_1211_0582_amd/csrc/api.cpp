@@ -392,6 +392,38 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream) {
   return DG_OK;
 }
 
+dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, int32_t reps, void* stream,
+                      double* ms) {
+  clear_error();
+  if (!p || !u || !rhs || !ms) return fail(DG_EINVAL, "null argument");
+  if (reps < 1 || warmup < 0) return fail(DG_EINVAL, "need reps >= 1 and warmup >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int32_t i = 0; i < warmup; ++i) {
+    dg_status st = dg_rhs(p, u, rhs, stream);
+    if (st != DG_OK) return st;
+  }
+  hipEvent_t e0, e1;
+  DG_HIP(hipEventCreate(&e0), "event create");
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    hipEventDestroy(e0);
+    return hip_fail(e, "event create");
+  }
+  dg_status st = DG_OK;
+  e = hipEventRecord(e0, s);
+  for (int32_t i = 0; i < reps && st == DG_OK && e == hipSuccess; ++i) st = dg_rhs(p, u, rhs, stream);
+  if (st == DG_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+  if (st == DG_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (st == DG_OK && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != DG_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "event timing");
+  *ms = double(t) / reps;
+  return DG_OK;
+}
+
 dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int32_t nsteps, void* stream) {
   clear_error();
   (void)t;

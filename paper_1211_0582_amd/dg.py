@@ -22,7 +22,7 @@ PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16x3": DG_BF16X3, "f16x3": DG
 
 #: every symbol the public headers declare
 EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",
-            "dg_destroy", "dg_last_error", "dg_variant_count", "dg_variant_name", "dg_set_variant",
+            "dg_destroy", "dg_last_error", "dg_variant_count", "dg_variant_name", "dg_set_variant", "dg_time_rhs",
             "dg_setup_batch", "dg_batch_problem", "dg_rk_step_batch", "dg_destroy_batch",
             "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
 
@@ -68,6 +68,7 @@ def _load():
         "dg_variant_count": (C.c_int32, []),
         "dg_variant_name": (C.c_char_p, [C.c_int32]),
         "dg_set_variant": (C.c_int, [P, C.c_int32]),
+        "dg_time_rhs": (C.c_int, [P, P, P, C.c_int32, C.c_int32, P, C.POINTER(C.c_double)]),
         "dg_setup_batch": (C.c_int, [C.c_int32, C.POINTER(MeshDesc), C.POINTER(P)]),
         "dg_batch_problem": (C.c_int, [P, C.c_int32, C.POINTER(P)]),
         "dg_rk_step_batch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double), C.c_int32, C.c_int32, P]),
@@ -209,6 +210,12 @@ def dg_variant_name(v):
     return None if n is None else n.decode()
 
 
+def dg_time_rhs(p, u, rhs, warmup=3, reps=20, stream=None):
+    ms = C.c_double()
+    _check(lib.dg_time_rhs(p, _ptr(u), _ptr(rhs), int(warmup), int(reps), _stream(stream), C.byref(ms)))
+    return ms.value
+
+
 def variant_id(name):
     for v in range(dg_variant_count()):
         if dg_variant_name(v) == name:
@@ -228,9 +235,15 @@ def dg_set_variant(p, v):
 class Problem:
     """Owns a dg_problem handle; allocates state arrays as torch tensors."""
 
-    def __init__(self, N, VX, EToV, precision="fp64", alpha=1.0):
+    def __init__(self, N, VX, EToV, precision="fp64", alpha=1.0, tuned=False):
+        """tuned: apply the variant the autotuner cache holds for (N, precision)."""
         self.handle = dg_setup_mesh(N, VX, EToV, precision, alpha)
         self.info = dg_info_get(self.handle)
+        if tuned:
+            from . import autotune
+            v = autotune.lookup(N, self.info.precision)
+            if v is not None:
+                self.set_variant(v)
 
     @property
     def torch_dtype(self):
