@@ -235,9 +235,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one torch copy of 256 MiB (scale for the HBM traffic counters)")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "sweep"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "sweep", "large"],
                     help="single: one mesh (default); batch: 64 independent problems stepped together; "
-                         "sweep: orders 1..9 at about 1e7 nodal values per field")
+                         "sweep: orders 1..9 at about 1e7 nodal values per field; "
+                         "large: 48^3 x 6 tets (K = 663,552), N = 5, FP32 and split precisions")
     ap.add_argument("--sweep-precisions", default="fp64,fp32,f16x3,bf16x3")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8,9")
     ap.add_argument("--traffic-file", default=None,
@@ -258,6 +259,12 @@ def main():
         return bench_batch(args, torch, dg)
     if args.workload == "sweep":
         return bench_sweep(args, torch, dg)
+    if args.workload == "large":
+        args.k, args.order = 48, 5
+        if args.precision == "fp64":
+            args.precision = "fp32"
+            args.also = "f16x3,bf16x3"
+        args.no_cpu_baseline = True
     N, k = args.order, args.k
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

@@ -2,6 +2,7 @@
 // this file once per order N = 1..9 with -DDG_ORDER=N (parallel builds, small
 // objects).
 #include "rhs_mfma.hpp"
+#include "rhs_mfma_p.hpp"
 #include "rhs_valu.hpp"
 
 #ifndef DG_ORDER
@@ -29,11 +30,18 @@ KernelSet make(int variant) {
       k.tile = 16;
       k.frag_count = MfmaShape<N>::frag_count;
     }
+  } else if (variant == kVariantMfmaP) {
+    if constexpr (persist_tpw<N, T, 0>() > 0) {
+      k.rhs = &launch_rhs_mfma_p<N, T>;
+      k.rk = &launch_rk_mfma_p<N, T>;
+      k.tile = 16;
+      k.frag_count = MfmaShape<N>::frag_count;
+    }
   }
   return k;
 }
 
-// Split 16-bit contraction (FP32 state): matrix-core variant only.
+// Split 16-bit contraction (FP32 state): matrix-core variants only.
 template <int MIX>
 KernelSet make_mixed(int variant) {
   constexpr int N = DG_ORDER;
@@ -42,6 +50,13 @@ KernelSet make_mixed(int variant) {
     if constexpr (mfma_supported<N, float>()) {
       k.rhs = &launch_rhs_mfma<N, float, MIX>;
       k.rk = &launch_rk_mfma<N, float, MIX>;
+      k.tile = 16;
+      k.frag16_bytes = MixedShape<N>::frag_bytes;
+    }
+  } else if (variant == kVariantMfmaP) {
+    if constexpr (persist_tpw<N, float, MIX>() > 0) {
+      k.rhs = &launch_rhs_mfma_p<N, float, MIX>;
+      k.rk = &launch_rk_mfma_p<N, float, MIX>;
       k.tile = 16;
       k.frag16_bytes = MixedShape<N>::frag_bytes;
     }

@@ -1,8 +1,9 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
 
 Every kernel variant ("valu": vector ALUs; "mfma": matrix cores with the
-Runge-Kutta stage fused into the epilogue) is compared with the oracle on the
-same seeded inputs.  Tolerances (max-norm, relative to the largest oracle
+Runge-Kutta stage fused into the epilogue; "mfma_p": the same contraction in
+persistent workgroups that walk a range of tiles) is compared with the oracle
+on the same seeded inputs.  Tolerances (max-norm, relative to the largest oracle
 value, padding excluded):
   FP64 right-hand side    1e-12  (the stated bar)
   FP64 100 LSERK steps    1e-10  (accumulated roundoff)
@@ -24,7 +25,7 @@ from oracle import mesh as Me
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ("valu", "mfma")
+VARIANTS = ("valu", "mfma", "mfma_p")
 TOL = {"fp64": 1e-12, "fp32": 5e-5}
 
 
@@ -271,24 +272,26 @@ SPLIT_TOL = {"bf16": 5e-1, "bf16x2": 5e-1, "bf16x3": 1e-3, "f16": 5e-2, "f16x2":
 SPLIT_TOL_FULL = {"bf16x3": 3e-3, "f16x3": 7e-5}
 
 
+@pytest.mark.parametrize("variant", ["mfma", "mfma_p"])
 @pytest.mark.parametrize("precision", list(SPLIT_TOL))
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7])
-def test_split_precision_rhs(dg, N, precision):
+def test_split_precision_rhs(dg, N, precision, variant):
     k = 3 if N <= 5 else 2
-    _say(f"[gpu] split rhs N={N} {precision}")
+    _say(f"[gpu] split rhs N={N} {precision} {variant}")
     VX, EToV, m, u, ref = _case(N, k)
-    got = _gpu_rhs(dg, N, VX, EToV, u, precision, "mfma")
+    got = _gpu_rhs(dg, N, VX, EToV, u, precision, variant)
     err = _rel(got, ref)
     _say(f"  {precision} N={N} rel err {err:.3e}")
     assert err < SPLIT_TOL[precision] * max(1.0, N / 4)
 
 
+@pytest.mark.parametrize("variant", ["mfma", "mfma_p"])
 @pytest.mark.parametrize("precision", ["bf16x3", "f16x3"])
-def test_split_precision_full_size_and_steps(dg, precision):
+def test_split_precision_full_size_and_steps(dg, precision, variant):
     import torch
-    _say(f"[gpu] split precision full size {precision}")
+    _say(f"[gpu] split precision full size {precision} {variant}")
     VX, EToV, m, u, ref = _case(4, 24)
-    got = _gpu_rhs(dg, 4, VX, EToV, u, precision, "mfma")
+    got = _gpu_rhs(dg, 4, VX, EToV, u, precision, variant)
     err = _rel(got, ref)
     _say(f"  {precision} K=82944 rel err {err:.3e}")
     assert err < SPLIT_TOL_FULL[precision]
@@ -297,7 +300,7 @@ def test_split_precision_full_size_and_steps(dg, precision):
     u0 = I.cavity_mode(mm.x, mm.y, mm.z)
     dt = D.dt_cfl(mm, 0.5)
     ref = L.integrate(lambda v, t: Mx.rhs(mm, v), u0, 0.0, dt, 20)
-    p = _problem(dg, 4, VX, EToV, precision, "mfma")
+    p = _problem(dg, 4, VX, EToV, precision, variant)
     du = p.pack(u0)
     res = p.zeros_state()
     p.rk_step(du, res, 0.0, dt, 20)
@@ -354,3 +357,51 @@ def test_batch_rejects_mixed_precision_and_unsupported(dg):
     descs = (dg.MeshDesc * 2)()
     with pytest.raises(dg.DgError):
         dg.Batch([(3, VX, EToV), (9, VX, EToV)], "fp64")   # FP64 N = 9 has no matrix-core kernel
+
+
+# ---------------------------------------------------------------------------
+# Large mesh: 48^3 x 6 tetrahedra (K = 663,552), N = 5, FP32 state (about
+# 0.9 GB per state array) -- the oracle on every element, and two properties
+# that hold at any size: the exact discrete energy identity and polynomial
+# exactness.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def large_case():
+    _say("[gpu] building the K=663552 N=5 oracle case")
+    VX, EToV = I.kuhn_cube(48, 0.1, 0)
+    m = Me.Mesh(5, VX, EToV)
+    u = I.cavity_mode(m.x, m.y, m.z) + I.field_noise((6, m.K, m.Np), 1e-3, 1)
+    ref = Mx.rhs(m, u)
+    diss = D.dissipation(m, u, 1.0)
+    scale = float(np.sum(m.J[None, :, None] * np.abs(u) * np.abs(ref @ m.re.M.T)))
+    return VX, EToV, m, u, ref, diss, scale
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("f16x3", 2e-4), ("bf16x3", 1e-2)])
+def test_large_mesh_against_oracle_and_energy_identity(dg, large_case, precision, tol):
+    _say(f"[gpu] large mesh K=663552 N=5 {precision}")
+    VX, EToV, m, u, ref, diss, scale = large_case
+    got = _gpu_rhs(dg, 5, VX, EToV, u, precision, "mfma")
+    err = _rel(got, ref)
+    _say(f"  {precision} rel err vs oracle {err:.3e}")
+    assert err < tol
+    # energy identity with the GPU right-hand side: sum_k J_k u^T M rhs
+    Mr = got @ m.re.M.T
+    rate = float(np.sum(m.J[None, :, None] * u * Mr))
+    _say(f"  energy rate {rate:.6e} vs dissipation {diss:.6e} (scale {scale:.3e})")
+    assert abs(rate - diss) < 10 * tol * scale
+
+
+def test_large_mesh_polynomial_exactness(dg, large_case):
+    _say("[gpu] large mesh polynomial exactness fp32")
+    VX, EToV, m = large_case[:3]
+    x, y = m.x, m.y
+    u = np.zeros((6, m.K, m.Np))
+    u[2] = x * (1 - x) * y * (1 - y)
+    got = _gpu_rhs(dg, 5, VX, EToV, u, "fp32", "mfma")
+    ex = np.zeros_like(u)
+    ex[3] = -x * (1 - x) * (1 - 2 * y)
+    ex[4] = (1 - 2 * x) * y * (1 - y)
+    err = float(np.abs(got - ex).max())
+    _say(f"  max abs err {err:.3e}")
+    assert err < 1e-4
