@@ -68,7 +68,7 @@ typedef enum {
  *   DG_BF16X2 / DG_F16X2:  a_hi b_hi + a_lo b_hi            (operator split)
  *   DG_BF16X3 / DG_F16X3:  a_hi b_hi + a_lo b_hi + a_hi b_lo (both split)
  *   where a is the operator and b the fields or fluxes; BF16 = bfloat16,
- *   F16 = IEEE binary16.  These have only the "mfma" variant.               */
+ *   F16 = IEEE binary16.  These have only the matrix-core variants.         */
 typedef enum {
   DG_FP64 = 0, DG_FP32 = 1, DG_BF16X3 = 2, DG_F16X3 = 3,
   DG_BF16 = 4, DG_F16 = 5, DG_BF16X2 = 6, DG_F16X2 = 7
@@ -130,7 +130,11 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
  *   0 "valu": one workgroup per element tile on the vector ALUs;
  *   1 "mfma": one wave per 16 elements, the contraction with
  *             [Dr|Ds|Dt|LIFT] on the matrix cores, Runge-Kutta stage fused
- *             into its epilogue.
+ *             into its epilogue;
+ *   2 "mfma_p": the same contraction in persistent workgroups (one per CU)
+ *             that walk a range of element tiles with the operator held in
+ *             LDS and the next tile's fields loaded behind the contraction
+ *             (built where four or two tiles and the operator fit in LDS).
  * dg_setup_mesh picks "mfma" where it is built for (N, precision), else
  * "valu".  dg_variant_name returns NULL outside 0 .. dg_variant_count()-1.
  * dg_set_variant: DG_EINVAL (null p, v out of range), DG_EUNSUPPORTED (not

@@ -116,13 +116,33 @@ struct MfmaTile {
   T face[16 * 4 * 4];                 // nx, ny, nz, Fscale / 2 per (element, face)
 };
 
+// Where the flux work of a tile runs relative to the contraction.  Flux
+// (gathers, jumps, upwind formula) is vector-ALU and memory work; the volume
+// loop keeps the matrix cores busy.  With IL the gathers are issued early in
+// the volume loop (behind a few steps of operator fragments already in
+// flight, since loads complete in issue order) and the flux iterations are
+// spread over the later volume steps, so the vector ALU works while the
+// matrix core does; without IL the flux phase runs between volume and lift.
+template <int NV, int NFI, int PRE>
+struct FluxSchedule {
+  static constexpr int first = PRE + 1;  // first step whose frag wait follows the gathers
+  // volume step after which flux iteration fi runs (NV: after the loop)
+  __device__ static constexpr int at(int fi) {
+    return first >= NV ? NV : first + (fi * (NV - first)) / NFI;
+  }
+};
+
 // Contraction of one wave.  H = 0 produces the E equations (curl H + LIFT fE),
 // H = 1 the H equations (-curl E + LIFT fH).  With V = H, (P, Q) = (dE, dH)
 // for H = 0 and V = -E, (P, Q) = (dH, -dE) for H = 1, the volume operand is
 // X_d = m_d x V and the flux f = 1/2 Fscale [ -n x Q + alpha (n (n.P) - P) ].
-template <int N, typename T, int H, typename FluxPhase>
-__device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&mr)[9], int lane, int64_t k0,
-                                 typename Mfma16<T>::acc (&acc)[MfmaShape<N>::RB][3], FluxPhase&& flux_phase) {
+// Flux work comes in three parts: gather() issues the neighbour loads,
+// flux_step(fi) evaluates flux iteration fi into registers, flux_store()
+// waits for the tile's readers and writes the fluxes over the field tile.
+template <int N, typename T, int H, bool IL, int NFI, typename Gather, typename FluxStep, typename FluxStore>
+__device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&mr)[9], int lane,
+                                 typename Mfma16<T>::acc (&acc)[MfmaShape<N>::RB][3], Gather&& gather,
+                                 FluxStep&& flux_step, FluxStore&& flux_store) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
@@ -138,9 +158,11 @@ __device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&
     for (int c = 0; c < 3; ++c) acc[ib][c] = acc_t{0, 0, 0, 0};
 
   // Software pipeline: global loads are issued kPre depth steps before use
-  // (one step when the accumulators already take most of the registers).
-  constexpr int kPre = RB >= 6 ? 1 : 2;
+  // (one step when the accumulators already take most of the registers;
+  // more when the gathers sit in the load queue behind them).
+  constexpr int kPre = IL ? (RB >= 4 ? 2 : 4) : (RB >= 6 ? 1 : 2);
   constexpr int NV = 3 * KSV;  // volume depth steps, ordered (ks, d)
+  using FS = FluxSchedule<NV, NFI, kPre>;
   const uint32_t lane_off = uint32_t(lane) * sz;
   auto frag_of = [&](int step, int ib) -> T {
     const int kg = step < NV ? (step % 3) * KSV + step / 3 : 3 * KSV + (step - NV);
@@ -168,6 +190,9 @@ __device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&
 #pragma unroll
         for (int ib = 0; ib < RB; ++ib) Abuf[(step + kPre) % (kPre + 1)][ib] = frag_of(step + kPre, ib);
       }
+      if constexpr (IL) {
+        if (step == 0) gather();
+      }
       const T mx = mr[3 * d], my = mr[3 * d + 1], mz = mr[3 * d + 2];
       T X[3];
       X[0] = my * v[2] - mz * v[1];
@@ -177,12 +202,25 @@ __device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&
       for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[ib][c] = M::mac(Abuf[step % (kPre + 1)][ib], X[c], acc[ib][c]);
+      if constexpr (IL) {
+#pragma unroll
+        for (int fi = 0; fi < NFI; ++fi)
+          if (FS::at(fi) == step) flux_step(fi);
+      }
     }
   }
+  if constexpr (IL) {
+#pragma unroll
+    for (int fi = 0; fi < NFI; ++fi)
+      if (FS::at(fi) >= NV) flux_step(fi);
+  } else {
+    gather();
+#pragma unroll
+    for (int fi = 0; fi < NFI; ++fi) flux_step(fi);
+  }
 
-  // Lifting: F (already scaled by Fscale / 2) comes from the LDS flux tile,
-  // which the workgroup's flux phase writes between the two phases.
-  flux_phase(t, k0);
+  // Lifting: F (already scaled by Fscale / 2) comes from the LDS flux tile.
+  flux_store();
   __syncthreads();
   constexpr int cb = H ? 3 : 0;
 #pragma unroll
@@ -255,9 +293,11 @@ __device__ inline void split4(const float (&x)[4], typename Mfma16x16<H16>::v4& 
   }
 }
 
-template <int N, typename H16, int NPROD, int H, typename FluxPhase>
+template <int N, typename H16, int NPROD, int H, bool IL, int NFI, typename Gather, typename FluxStep,
+          typename FluxStore>
 __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane,
-                                  int64_t k0, f32x4 (&acc)[MfmaShape<N>::RB][3], FluxPhase&& flux_phase) {
+                                  f32x4 (&acc)[MfmaShape<N>::RB][3], Gather&& gather, FluxStep&& flux_step,
+                                  FluxStore&& flux_store) {
   using S = MfmaShape<N>;
   using X = MixedShape<N>;
   using MM = Mfma16x16<H16>;
@@ -273,6 +313,7 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
 
   // A fragments (head, tail) prefetched kPre steps ahead.
   constexpr int kPre = 2;
+  using FS = FluxSchedule<SV, NFI, kPre>;
   auto frag_of = [&](int step, int ib, v4& hi, v4& lo) {
     const uint32_t off = uint32_t(((ib * ST + step) * 64 + lane) * 16);
     const auto w = __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 0, 0);
@@ -308,6 +349,9 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
 #pragma unroll
       for (int ib = 0; ib < RB; ++ib) frag_of(s + kPre, ib, Ahi[(s + kPre) % (kPre + 1)][ib], Alo[(s + kPre) % (kPre + 1)][ib]);
     }
+    if constexpr (IL) {
+      if (s == 0) gather();
+    }
     const int kap = 16 * s + 4 * q;
     float xv[3][4];
     if (kap < 3 * Np4) {
@@ -332,10 +376,24 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
 #pragma unroll
     for (int c = 0; c < 3; ++c) split4<H16>(xv[c], bh[c], bl[c]);
     mma(s, bh, bl);
+    if constexpr (IL) {
+#pragma unroll
+      for (int fi = 0; fi < NFI; ++fi)
+        if (FS::at(fi) == s) flux_step(fi);
+    }
+  }
+  if constexpr (IL) {
+#pragma unroll
+    for (int fi = 0; fi < NFI; ++fi)
+      if (FS::at(fi) >= SV) flux_step(fi);
+  } else {
+    gather();
+#pragma unroll
+    for (int fi = 0; fi < NFI; ++fi) flux_step(fi);
   }
 
   // Lifting: fluxes from the LDS flux tile written by the workgroup.
-  flux_phase(t, k0);
+  flux_store();
   __syncthreads();
   constexpr int cb = H ? 3 : 0;
 #pragma unroll
@@ -357,6 +415,18 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
     for (int c = 0; c < 3; ++c) split4<H16>(fv[c], bh[c], bl[c]);
     mma(step, bh, bl);
   }
+}
+
+// Whether a tile's flux work is interleaved with its volume contraction (see
+// FluxSchedule): the neighbour traces, then the fluxes computed from them
+// (6 scalars per flux iteration), stay in registers through the volume loop.
+#ifndef DG_FLUX_IL
+#define DG_FLUX_IL 1
+#endif
+template <int N, typename T, int MIX>
+constexpr bool flux_interleaved() {
+  constexpr int iters = (16 * MfmaShape<N>::NF + 127) / 128;
+  return DG_FLUX_IL && iters * 6 * sizeof(T) / 4 <= 72;
 }
 
 // Workgroup = two waves sharing one tile of 16 elements; wave h = 0 produces
@@ -462,74 +532,76 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   constexpr int kPairs = 16 * NF;
   constexpr int kFluxIters = (kPairs + 127) / 128;
   const T alpha = T(a.alpha);
-  auto flux_phase = [&](MfmaTile<N, T>& tt, int64_t) {
-    T gx[kFluxIters][6];
+  T gx[kFluxIters][6];
+  T fl[kFluxIters][6];
+  auto gather = [&]() {
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
       const int pr = tid + 128 * it;
       const int ee = pr & 15, m = pr >> 4;
       const int f = m / Nfp, jj = m - f * Nfp;
-      const int32_t cf = (pr < kPairs) ? tt.code[4 * ee + f] : -1;
+      const int32_t cf = (pr < kPairs) ? t.code[4 * ee + f] : -1;
       // interior: neighbour node; wall: own node (mirror applied below); dead: zero
       uint32_t vo = kOob;
       if (pr < kPairs && ee < ne)
-        vo = uint32_t(cf >= 0 ? int64_t(cf >> 5) * Np + tt.nbr[(f * 24 + (cf & 31)) * Nfp + jj]
-                              : (k0 + ee) * Np + tt.fmask[m]) * sz;
+        vo = uint32_t(cf >= 0 ? int64_t(cf >> 5) * Np + t.nbr[(f * 24 + (cf & 31)) * Nfp + jj]
+                              : (k0 + ee) * Np + t.fmask[m]) * sz;
 #pragma unroll
       for (int c = 0; c < 6; ++c) gx[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
     }
-    T fl[kFluxIters][6];
+  };
+  auto flux_step = [&](int it) {
+    const int pr = tid + 128 * it;
+    const int ee = pr & 15, m = pr >> 4;
+    if (pr < kPairs) {
+      const int f = m / Nfp;
+      const int own = t.fmask[m];
+      const T se = t.code[4 * ee + f] < 0 ? T(-1) : T(1);  // wall: E+ = -E-, H+ = H-
+      T d[6];
 #pragma unroll
-    for (int it = 0; it < kFluxIters; ++it) {
-      const int pr = tid + 128 * it;
-      const int ee = pr & 15, m = pr >> 4;
-      if (pr < kPairs) {
-        const int f = m / Nfp;
-        const int own = tt.fmask[m];
-        const T se = tt.code[4 * ee + f] < 0 ? T(-1) : T(1);  // wall: E+ = -E-, H+ = H-
-        T d[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          const T em = tt.su[(c * Np4 + own) * TS + ee];
-          d[c] = c < 3 ? em - se * gx[it][c] : em - gx[it][c];
-        }
-        const T* fr = &tt.face[4 * (4 * ee + f)];
-        const T nx = fr[0], ny = fr[1], nz = fr[2], sc = fr[3];
-        const T ndE = nx * d[0] + ny * d[1] + nz * d[2];
-        const T ndH = nx * d[3] + ny * d[4] + nz * d[5];
-        fl[it][0] = sc * (-(ny * d[5] - nz * d[4]) + alpha * (nx * ndE - d[0]));
-        fl[it][1] = sc * (-(nz * d[3] - nx * d[5]) + alpha * (ny * ndE - d[1]));
-        fl[it][2] = sc * (-(nx * d[4] - ny * d[3]) + alpha * (nz * ndE - d[2]));
-        fl[it][3] = sc * ((ny * d[2] - nz * d[1]) + alpha * (nx * ndH - d[3]));
-        fl[it][4] = sc * ((nz * d[0] - nx * d[2]) + alpha * (ny * ndH - d[4]));
-        fl[it][5] = sc * ((nx * d[1] - ny * d[0]) + alpha * (nz * ndH - d[5]));
+      for (int c = 0; c < 6; ++c) {
+        const T em = t.su[(c * Np4 + own) * TS + ee];
+        d[c] = c < 3 ? em - se * gx[it][c] : em - gx[it][c];
       }
+      const T* fr = &t.face[4 * (4 * ee + f)];
+      const T nx = fr[0], ny = fr[1], nz = fr[2], sc = fr[3];
+      const T ndE = nx * d[0] + ny * d[1] + nz * d[2];
+      const T ndH = nx * d[3] + ny * d[4] + nz * d[5];
+      fl[it][0] = sc * (-(ny * d[5] - nz * d[4]) + alpha * (nx * ndE - d[0]));
+      fl[it][1] = sc * (-(nz * d[3] - nx * d[5]) + alpha * (ny * ndE - d[1]));
+      fl[it][2] = sc * (-(nx * d[4] - ny * d[3]) + alpha * (nz * ndE - d[2]));
+      fl[it][3] = sc * ((ny * d[2] - nz * d[1]) + alpha * (nx * ndH - d[3]));
+      fl[it][4] = sc * ((nz * d[0] - nx * d[2]) + alpha * (ny * ndH - d[4]));
+      fl[it][5] = sc * ((nx * d[1] - ny * d[0]) + alpha * (nz * ndH - d[5]));
     }
-    __syncthreads();  // every own-trace read is done before the tile is overwritten
+  };
+  auto flux_store = [&]() {
+    __syncthreads();  // every read of the field tile is done before it is overwritten
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
       const int pr = tid + 128 * it;
       const int ee = pr & 15, m = pr >> 4;
       if (pr < kPairs) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) tt.su[(c * NF + m) * TS + ee] = fl[it][c];
+        for (int c = 0; c < 6; ++c) t.su[(c * NF + m) * TS + ee] = fl[it][c];
       }
     }
   };
 
+  constexpr bool IL = flux_interleaved<N, T, MIX>();
   acc_t acc[RB][3];
   if constexpr (MIX == 0) {
     if (h == 0)
-      mfma_wave<N, T, 0>(a, t, mr, lane, k0, acc, flux_phase);
+      mfma_wave<N, T, 0, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
     else
-      mfma_wave<N, T, 1>(a, t, mr, lane, k0, acc, flux_phase);
+      mfma_wave<N, T, 1, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
   } else {
     using H16 = typename std::conditional<(MIX <= 3), __bf16, _Float16>::type;
     constexpr int NPROD = MIX <= 3 ? MIX : MIX - 3;
     if (h == 0)
-      mixed_wave<N, H16, NPROD, 0>(a, t, mr, lane, k0, acc, flux_phase);
+      mixed_wave<N, H16, NPROD, 0, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
     else
-      mixed_wave<N, H16, NPROD, 1>(a, t, mr, lane, k0, acc, flux_phase);
+      mixed_wave<N, H16, NPROD, 1, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
   }
 
   // Epilogue through LDS: [c][e][i] for this wave's three fields, then
