@@ -420,13 +420,15 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
 // Whether a tile's flux work is interleaved with its volume contraction (see
 // FluxSchedule): the neighbour traces, then the fluxes computed from them
 // (6 scalars per flux iteration), stay in registers through the volume loop.
-#ifndef DG_FLUX_IL
-#define DG_FLUX_IL 1
-#endif
+// Measured on MI355X it pays in FP64 (7% at N = 3, the order where the
+// registers allow it); in FP32 and the split precisions it costs a wave per
+// SIMD and gains nothing: the FP32 matrix and vector pipes never co-issue
+// (SQ_VALU_MFMA_COEXEC_CYCLES reads 0), and the split forms are bound by the
+// vector ALU already.
 template <int N, typename T, int MIX>
 constexpr bool flux_interleaved() {
   constexpr int iters = (16 * MfmaShape<N>::NF + 127) / 128;
-  return DG_FLUX_IL && iters * 6 * sizeof(T) / 4 <= 72;
+  return sizeof(T) == 8 && iters * 6 * sizeof(T) / 4 <= 72;
 }
 
 // Workgroup = two waves sharing one tile of 16 elements; wave h = 0 produces
