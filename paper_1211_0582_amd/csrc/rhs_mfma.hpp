@@ -84,7 +84,7 @@ constexpr size_t mfma_lds_bytes() {
 // accumulators (RB * 3 * 4 scalars per lane) must fit.
 template <int N, typename T>
 constexpr bool mfma_supported() {
-  return mfma_lds_bytes<N, T>() <= 65536 && MfmaShape<N>::RB * 3 * 4 * sizeof(T) / 4 <= 128;
+  return mfma_lds_bytes<N, T>() <= 160 * 1024 && MfmaShape<N>::RB * 3 * 4 * sizeof(T) / 4 <= 128;
 }
 
 // Raw buffer loads: a 128-bit resource (base, size) in SGPRs plus a 32-bit
