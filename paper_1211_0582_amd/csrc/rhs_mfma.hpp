@@ -67,12 +67,17 @@ struct MfmaShape {
   static constexpr int KSV = Np4 / 4;         // depth steps per direction
   static constexpr int KSL = NF / 4;          // depth steps of LIFT (4 Nfp is a multiple of 4)
   static constexpr int KS = 3 * KSV + KSL;
-  static constexpr int TS = 17;               // LDS row stride (16 elements + 1)
+  // LDS row strides: field rows TS = 17 (16 elements + 1, so that the
+  // tile store, which walks consecutive rows of one element, spreads over
+  // the banks); flux rows TQ = 16 (written and read 64 entries at a time in
+  // row order, conflict-free without padding, and one workgroup more fits
+  // per CU at N = 3, 4).
+  static constexpr int TS = 17, TQ = 16;
   static constexpr int frag_count = RB * KS * 64;
   // The LDS tile holds the fields [c][Np4][TS] first, then the fluxes
-  // [c][NF][TS], then the output staging [c][16][Np].
-  static constexpr int ROWS = Np4 > NF ? Np4 : NF;
-  static constexpr int TILE = 6 * ROWS * TS;
+  // [c][NF][TQ], then the output staging [c][16][Np].
+  static constexpr int FIELDS = 6 * Np4 * TS, FLUXES = 6 * NF * TQ, STAGE = 6 * 16 * Np;
+  static constexpr int TILE = FIELDS > FLUXES ? (FIELDS > STAGE ? FIELDS : STAGE) : (FLUXES > STAGE ? FLUXES : STAGE);
 };
 
 template <int N, typename T>
@@ -147,7 +152,7 @@ __device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
   constexpr int Np4 = S::Np4, NF = S::NF, RB = S::RB, KSV = S::KSV, KSL = S::KSL;
-  constexpr int KS = S::KS, TS = S::TS;
+  constexpr int KS = S::KS, TS = S::TS, TQ = S::TQ;
   constexpr uint32_t sz = sizeof(T);
   const int e = lane & 15, q = lane >> 4;
   const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag, uint32_t(RB * KS * 64) * sz);
@@ -233,7 +238,7 @@ __device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&
     const int m = 4 * ks + q;
     T F[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) F[c] = t.su[((cb + c) * NF + m) * TS + e];
+    for (int c = 0; c < 3; ++c) F[c] = t.su[((cb + c) * NF + m) * TQ + e];
 #pragma unroll
     for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
@@ -302,7 +307,7 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
   using X = MixedShape<N>;
   using MM = Mfma16x16<H16>;
   using v4 = typename MM::v4;
-  constexpr int Np4 = S::Np4, NF = S::NF, RB = S::RB, TS = S::TS;
+  constexpr int Np4 = S::Np4, NF = S::NF, RB = S::RB, TS = S::TS, TQ = S::TQ;
   constexpr int SV = X::SV, SL = X::SL, ST = X::ST;
   const int e = lane & 15, q = lane >> 4;
   const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag16, uint32_t(X::frag_bytes));
@@ -409,7 +414,7 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) fv[c][v] = (m + v < NF) ? t.su[((cb + c) * NF + m + v) * TS + e] : 0.f;
+      for (int v = 0; v < 4; ++v) fv[c][v] = (m + v < NF) ? t.su[((cb + c) * NF + m + v) * TQ + e] : 0.f;
     v4 bh[3], bl[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) split4<H16>(fv[c], bh[c], bl[c]);
@@ -441,7 +446,7 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
-  constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, TS = S::TS;
+  constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, TS = S::TS, TQ = S::TQ;
   __shared__ MfmaTile<N, T> t;
 
   const int64_t fs = a.fs;
@@ -585,7 +590,7 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
       const int ee = pr & 15, m = pr >> 4;
       if (pr < kPairs) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t.su[(c * NF + m) * TS + ee] = fl[it][c];
+        for (int c = 0; c < 6; ++c) t.su[(c * NF + m) * TQ + ee] = fl[it][c];
       }
     }
   };

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(128 * TPW) void rhs_mfma_p_kernel(RhsArgs a, int pe
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
   constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, KSV = S::KSV, KSL = S::KSL;
-  constexpr int KS = S::KS, TS = S::TS;
+  constexpr int KS = S::KS, TS = S::TS, TQ = S::TQ;
   constexpr uint32_t sz = sizeof(T);
   constexpr uint32_t kOob = 0x80000000u;
   __shared__ PersistShared<N, T, MIX, TPW> sh;
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(128 * TPW) void rhs_mfma_p_kernel(RhsArgs a, int pe
       const int ee = pr & 15, m = pr >> 4;
       if (pr < kPairs) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sl.su[(c * NF + m) * TS + ee] = fl[fi][c];
+        for (int c = 0; c < 6; ++c) sl.su[(c * NF + m) * TQ + ee] = fl[fi][c];
       }
     }
     __syncthreads();
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(128 * TPW) void rhs_mfma_p_kernel(RhsArgs a, int pe
         const int kg = 3 * KSV + ks;
         T F[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) F[c] = sl.su[((cb + c) * NF + m) * TS + e];
+        for (int c = 0; c < 3; ++c) F[c] = sl.su[((cb + c) * NF + m) * TQ + e];
 #pragma unroll
         for (int ib = 0; ib < RB; ++ib) {
           const T A = fr[(ib * KS + kg) * 64 + lane];
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(128 * TPW) void rhs_mfma_p_kernel(RhsArgs a, int pe
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) fv[c][v] = (m + v < NF) ? sl.su[((cb + c) * NF + m + v) * TS + e] : 0.f;
+          for (int v = 0; v < 4; ++v) fv[c][v] = (m + v < NF) ? sl.su[((cb + c) * NF + m + v) * TQ + e] : 0.f;
         v4 bh[3], bl[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) split4<H16>(fv[c], bh[c], bl[c]);
