@@ -405,3 +405,63 @@ def test_large_mesh_polynomial_exactness(dg, large_case):
     err = float(np.abs(got - ex).max())
     _say(f"  max abs err {err:.3e}")
     assert err < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# End to end on the GPU: time integration of the cavity mode against its
+# closed form (h-convergence at the rate the method gives, N + 1 in theory,
+# N + 1/2 guaranteed), and the discrete energy never increasing under the
+# upwind flux.  The errors and energies are measured by the oracle's mass
+# norm on the unpacked GPU states.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N,precision,ks,cfl,expect", [
+    (2, "fp64", (2, 4, 8), 0.5, 2.5),
+    (3, "fp64", (2, 4, 8), 0.5, 3.5),
+    (4, "fp64", (2, 4), 0.125, 4.5),
+    (3, "fp32", (2, 4), 0.5, 3.3),
+    (3, "f16x3", (2, 4), 0.5, 3.3),
+])
+def test_gpu_cavity_h_convergence(dg, N, precision, ks, cfl, expect):
+    import torch
+    T = 0.25
+    errs = []
+    for k in ks:
+        _say(f"[gpu] cavity convergence N={N} k={k} {precision}")
+        VX, EToV = I.kuhn_cube(k, 0.1, k)
+        m = Me.Mesh(N, VX, EToV)
+        u0 = I.cavity_mode(m.x, m.y, m.z, 0.0)
+        ns = int(np.ceil(T / D.dt_cfl(m, cfl)))
+        p = dg.Problem(N, VX, EToV, precision)
+        du = p.pack(u0)
+        res = p.zeros_state()
+        p.rk_step(du, res, 0.0, T / ns, ns)
+        torch.cuda.synchronize()
+        u = p.unpack(du)
+        p.close()
+        ex = I.cavity_mode(m.x, m.y, m.z, T)
+        errs.append(D.mass_norm(m, u - ex) / D.mass_norm(m, u0))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    _say(f"  errors {['%.3e' % e for e in errs]} rates {['%.2f' % r for r in rates]}")
+    assert rates[-1] > expect
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gpu_energy_non_increasing(dg, precision):
+    import torch
+    _say(f"[gpu] energy over 100 LSERK steps {precision}")
+    VX, EToV = I.kuhn_cube(4, 0.1, 0)
+    m = Me.Mesh(3, VX, EToV)
+    u0 = I.cavity_mode(m.x, m.y, m.z) + I.field_noise((6, m.K, m.Np), 1e-3, 1)
+    dt = D.dt_cfl(m, 0.5)
+    p = dg.Problem(3, VX, EToV, precision)
+    du = p.pack(u0)
+    res = p.zeros_state()
+    energies = [D.energy(m, p.unpack(du))]
+    for _ in range(10):
+        p.rk_step(du, res, 0.0, dt, 10)
+        torch.cuda.synchronize()
+        energies.append(D.energy(m, p.unpack(du)))
+    p.close()
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    assert np.all(np.diff(energies) <= tol * energies[0])
+    assert energies[-1] < energies[0]
