@@ -78,6 +78,17 @@ struct MfmaShape {
   // [c][NF][TQ], then the output staging [c][16][Np].
   static constexpr int FIELDS = 6 * Np4 * TS, FLUXES = 6 * NF * TQ, STAGE = 6 * 16 * Np;
   static constexpr int TILE = FIELDS > FLUXES ? (FIELDS > STAGE ? FIELDS : STAGE) : (FLUXES > STAGE ? FLUXES : STAGE);
+  // Split lift: the fluxes go to LDS and are lifted in two halves of face
+  // nodes, m < HB and m >= HB, through a region of 6 x HB rows.  The flux
+  // phase covers 8 face-node rows per 128-lane iteration, so HB is a whole
+  // number of iterations (and of 4-row depth steps).
+  static constexpr int FLUX_ITERS = (16 * NF + 127) / 128;
+  static constexpr int HALF_ITERS = (FLUX_ITERS + 1) / 2;
+  static constexpr int HB = 8 * HALF_ITERS;
+  static constexpr int tile(bool half) {
+    const int f = half ? 6 * HB * TQ : FLUXES;
+    return FIELDS > f ? (FIELDS > STAGE ? FIELDS : STAGE) : (f > STAGE ? f : STAGE);
+  }
 };
 
 template <int N, typename T>
@@ -111,10 +122,11 @@ __device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t vof
 }
 
 // State shared by the two waves of a workgroup.
-template <int N, typename T>
+template <int N, typename T, bool HALF = false>
 struct MfmaTile {
   using S = MfmaShape<N>;
-  T su[S::TILE];                      // fields [c][j][e], then fluxes [c][m][e], then output
+  static constexpr bool kHalf = HALF;
+  T su[S::tile(HALF)];                // fields [c][j][e], then fluxes [c][m][e], then output
   int16_t fmask[S::NF];
   alignas(16) uint8_t nbr[(4 * 24 * S::Nfp + 15) / 16 * 16];
   int32_t code[16 * 4];               // face codes of the tile's elements
@@ -144,8 +156,9 @@ struct FluxSchedule {
 // Flux work comes in three parts: gather() issues the neighbour loads,
 // flux_step(fi) evaluates flux iteration fi into registers, flux_store()
 // waits for the tile's readers and writes the fluxes over the field tile.
-template <int N, typename T, int H, bool IL, int NFI, typename Gather, typename FluxStep, typename FluxStore>
-__device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&mr)[9], int lane,
+template <int N, typename T, int H, bool IL, int NFI, typename Tile, typename Gather, typename FluxStep,
+          typename FluxStore>
+__device__ inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], int lane,
                                  typename Mfma16<T>::acc (&acc)[MfmaShape<N>::RB][3], Gather&& gather,
                                  FluxStep&& flux_step, FluxStore&& flux_store) {
   using S = MfmaShape<N>;
@@ -224,25 +237,41 @@ __device__ inline void mfma_wave(const RhsArgs& a, MfmaTile<N, T>& t, const T (&
     for (int fi = 0; fi < NFI; ++fi) flux_step(fi);
   }
 
-  // Lifting: F (already scaled by Fscale / 2) comes from the LDS flux tile.
-  flux_store();
-  __syncthreads();
+  // Lifting: F (already scaled by Fscale / 2) comes from the LDS flux tile,
+  // in one pass or, with the split lift, in two halves of face-node rows.
   constexpr int cb = H ? 3 : 0;
+  constexpr bool HALF = Tile::kHalf;
+  constexpr int FR = HALF ? S::HB : NF;  // rows per component in the flux region
+  auto lift = [&](int ks0, int ks1, int base) {
 #pragma unroll
-  for (int ks = 0; ks < KSL; ++ks) {
-    const int step = NV + ks;
-    if (step + kPre < KS) {
+    for (int ks = ks0; ks < ks1; ++ks) {
+      const int step = NV + ks;
+      if (step + kPre < KS) {
 #pragma unroll
-      for (int ib = 0; ib < RB; ++ib) Abuf[(step + kPre) % (kPre + 1)][ib] = frag_of(step + kPre, ib);
+        for (int ib = 0; ib < RB; ++ib) Abuf[(step + kPre) % (kPre + 1)][ib] = frag_of(step + kPre, ib);
+      }
+      const int m = 4 * ks + q - base;
+      T F[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] = t.su[((cb + c) * FR + m) * TQ + e];
+#pragma unroll
+      for (int ib = 0; ib < RB; ++ib)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[ib][c] = M::mac(Abuf[step % (kPre + 1)][ib], F[c], acc[ib][c]);
     }
-    const int m = 4 * ks + q;
-    T F[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) F[c] = t.su[((cb + c) * NF + m) * TQ + e];
-#pragma unroll
-    for (int ib = 0; ib < RB; ++ib)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[ib][c] = M::mac(Abuf[step % (kPre + 1)][ib], F[c], acc[ib][c]);
+  };
+  if constexpr (!HALF) {
+    flux_store(-1);
+    __syncthreads();
+    lift(0, KSL, 0);
+  } else {
+    flux_store(0);
+    __syncthreads();
+    lift(0, S::HB / 4, 0);
+    __syncthreads();  // first half read before the second overwrites it
+    flux_store(1);
+    __syncthreads();
+    lift(S::HB / 4, KSL, S::HB);
   }
 }
 
@@ -398,7 +427,7 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
   }
 
   // Lifting: fluxes from the LDS flux tile written by the workgroup.
-  flux_store();
+  flux_store(-1);
   __syncthreads();
   constexpr int cb = H ? 3 : 0;
 #pragma unroll
@@ -436,6 +465,15 @@ constexpr bool flux_interleaved() {
   return sizeof(T) == 8 && iters * 6 * sizeof(T) / 4 <= 72;
 }
 
+// Whether the lift runs in two halves (see MfmaShape::tile): it trades two
+// barriers for a smaller flux region.  Used where the flux region sets the
+// LDS size and the registers allow one more workgroup per CU once it
+// shrinks: FP64 at N = 4 (3 -> 4 workgroups per CU).
+template <int N, typename T, int MIX>
+constexpr bool lift_split() {
+  return MIX == 0 && sizeof(T) == 8 && N == 4;
+}
+
 // Workgroup = two waves sharing one tile of 16 elements; wave h = 0 produces
 // the E equations, wave h = 1 the H equations (see mfma_wave).
 // MIX = 0: contraction in T on 16x16x4 MFMAs; MIX = 1..3: T = float with the
@@ -447,7 +485,8 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
   constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, TS = S::TS, TQ = S::TQ;
-  __shared__ MfmaTile<N, T> t;
+  constexpr bool LIFT_HALF = lift_split<N, T, MIX>();
+  __shared__ MfmaTile<N, T, LIFT_HALF> t;
 
   const int64_t fs = a.fs;
   const int tid = threadIdx.x;
@@ -582,15 +621,23 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
       fl[it][5] = sc * ((nx * d[1] - ny * d[0]) + alpha * (nz * ndH - d[5]));
     }
   };
-  auto flux_store = [&]() {
-    __syncthreads();  // every read of the field tile is done before it is overwritten
+  // part -1: all fluxes, rows c NF + m; part 0 / 1 (split lift): the flux
+  // iterations of the first / second half of face-node rows, rows
+  // c HB + m - part HB.  Parts -1 and 0 first wait until every read of the
+  // field tile is done, since the fluxes overwrite it.
+  auto flux_store = [&](int part) {
+    constexpr int FR = LIFT_HALF ? S::HB : NF;
+    if (part <= 0) __syncthreads();
+    const int it0 = part == 1 ? S::HALF_ITERS : 0;
+    const int it1 = part == 0 ? S::HALF_ITERS : kFluxIters;
+    const int base = part == 1 ? S::HB : 0;
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
       const int pr = tid + 128 * it;
       const int ee = pr & 15, m = pr >> 4;
-      if (pr < kPairs) {
+      if (it >= it0 && it < it1 && pr < kPairs) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t.su[(c * NF + m) * TQ + ee] = fl[it][c];
+        for (int c = 0; c < 6; ++c) t.su[(c * FR + m - base) * TQ + ee] = fl[it][c];
       }
     }
   };
