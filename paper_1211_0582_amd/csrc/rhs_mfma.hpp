@@ -1,23 +1,26 @@
-// Fused DG Maxwell right-hand side on the matrix cores (FP64 / FP32 MFMA).
+// Fused DG Maxwell right-hand side on the matrix cores (FP64 / FP32 MFMA,
+// and split 16-bit contractions with FP32 accumulation).
 //
 // The operator of Section 2 is, per element, one dense contraction:
 //   rhs[c][i] = sum_d sum_j D_d[i][j] X_d[c][j] + sum_m LIFT[i][m] F[c][m]
 // with X_d = (m_d x H, E x m_d) the fields pre-combined with the element's
 // constant metric row m_d = (d_x, d_y, d_z), d in {r, s, t} (so the volume
 // sum is the curl term of Section 2.1), and F the Fscale-scaled upwind flux
-// at the 4 Nfp face nodes.  One wave owns 16 elements and runs that
-// contraction as 16x16x4 MFMAs: rows = nodes i (Np padded to 16), columns =
-// the 16 elements, depth = [Dr | Ds | Dt | LIFT] columns (each padded to 4).
+// at the 4 Nfp face nodes.  A workgroup of two waves owns a tile of 16
+// elements: wave 0 produces the E equations, wave 1 the H equations, each as
+// MFMAs with rows = nodes i (Np padded to 16), columns = the 16 elements,
+// depth = [Dr | Ds | Dt | LIFT] columns (each padded to 4).
 //
 //  * The operator is pre-swizzled on the host into MFMA A-fragments
 //    (row block ib, depth step kg, lane) and streamed through L1/L2 (one
-//    coalesced load feeds six MFMAs, one per output component).
+//    coalesced load feeds three MFMAs, one per output component).
 //  * The tile's fields sit in LDS as [c][j][e] (16 elements fastest), read in
 //    B-fragment layout; X_d is formed in registers.
-//  * The flux gather happens directly in B-fragment layout: lane (e, m)
-//    gathers the neighbour trace through the orientation table, evaluates the
-//    flux and feeds it to the LIFT MFMAs -- the facial buffer of the paper's
-//    split pipeline never exists.
+//  * The flux is evaluated once per (element, face node) by all 128 lanes:
+//    the neighbour trace comes through the orientation table (a wall reads
+//    the own node and mirrors it), and the fluxes are staged in LDS in
+//    B-fragment order over the field tile for the LIFT MFMAs -- the facial
+//    buffer of the paper's split pipeline never reaches HBM.
 //  * Epilogue: accumulators go through LDS to coalesced stores; in the
 //    Runge-Kutta mode the stage update res <- a res + dt rhs,
 //    u_out <- u + b res is applied there (u_out is a second state buffer, as
