@@ -94,16 +94,32 @@ struct MfmaShape {
   }
 };
 
+// Waves per tile: 2 (wave 0 the E equations, wave 1 the H equations, all row
+// blocks each) or 4 (the same two roles, each split over two waves by row
+// blocks).  Four halves the accumulators and operator-fragment traffic per
+// wave, which at high order is what bounds the waves per SIMD, at the price
+// of forming the volume operand twice (N = 7, FP32: 1 -> 2 waves per SIMD,
+// 42% -> 55% of peak).
+template <int N, typename T, int MIX>
+constexpr int waves_per_tile() {
+  constexpr int RB = MfmaShape<N>::RB;
+  // The split forms pay for the duplicated operand split; measured on
+  // MI355X four waves win from N = 5 for FP64/FP32 and from N = 6 for them.
+  constexpr int min_rb = MIX == 0 ? 4 : 6;
+  return (RB >= min_rb && RB % 2 == 0) ? 4 : 2;
+}
+
 template <int N, typename T>
 constexpr size_t mfma_lds_bytes() {
   return size_t(MfmaShape<N>::TILE) * sizeof(T);
 }
 
 // Whether the MFMA variant is built for (N, T): the LDS tile and the
-// accumulators (RB * 3 * 4 scalars per lane) must fit.
+// accumulators (row blocks per wave x 3 x 4 scalars per lane) must fit.
 template <int N, typename T>
 constexpr bool mfma_supported() {
-  return mfma_lds_bytes<N, T>() <= 160 * 1024 && MfmaShape<N>::RB * 3 * 4 * sizeof(T) / 4 <= 128;
+  constexpr int RBW = MfmaShape<N>::RB * 2 / waves_per_tile<N, T, 0>();  // row blocks per wave
+  return mfma_lds_bytes<N, T>() <= 160 * 1024 && RBW * 3 * 4 * sizeof(T) / 4 <= 128;
 }
 
 // Raw buffer loads: a 128-bit resource (base, size) in SGPRs plus a 32-bit
@@ -159,19 +175,21 @@ struct FluxSchedule {
 // Flux work comes in three parts: gather() issues the neighbour loads,
 // flux_step(fi) evaluates flux iteration fi into registers, flux_store()
 // waits for the tile's readers and writes the fluxes over the field tile.
-template <int N, typename T, int H, bool IL, int NFI, typename Tile, typename Gather, typename FluxStep,
+// The wave produces row blocks rb0 .. rb0 + RBW - 1 of its three components
+// (all RB blocks with two waves per tile, half of them with four).
+template <int N, typename T, int H, bool IL, int NFI, int RBW, typename Tile, typename Gather, typename FluxStep,
           typename FluxStore>
-__device__ inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], int lane,
-                                 typename Mfma16<T>::acc (&acc)[MfmaShape<N>::RB][3], Gather&& gather,
+__device__ inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], int lane, int rb0,
+                                 typename Mfma16<T>::acc (&acc)[RBW][3], Gather&& gather,
                                  FluxStep&& flux_step, FluxStore&& flux_store) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
-  constexpr int Np4 = S::Np4, NF = S::NF, RB = S::RB, KSV = S::KSV, KSL = S::KSL;
+  constexpr int Np4 = S::Np4, NF = S::NF, RB = RBW, KSV = S::KSV, KSL = S::KSL;
   constexpr int KS = S::KS, TS = S::TS, TQ = S::TQ;
   constexpr uint32_t sz = sizeof(T);
   const int e = lane & 15, q = lane >> 4;
-  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag, uint32_t(RB * KS * 64) * sz);
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag, uint32_t(S::RB * KS * 64) * sz);
 
 #pragma unroll
   for (int ib = 0; ib < RB; ++ib)
@@ -184,7 +202,7 @@ __device__ inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], in
   constexpr int kPre = IL ? (RB >= 4 ? 2 : 4) : (RB >= 6 ? 1 : 2);
   constexpr int NV = 3 * KSV;  // volume depth steps, ordered (ks, d)
   using FS = FluxSchedule<NV, NFI, kPre>;
-  const uint32_t lane_off = uint32_t(lane) * sz;
+  const uint32_t lane_off = uint32_t(lane + rb0 * KS * 64) * sz;
   auto frag_of = [&](int step, int ib) -> T {
     const int kg = step < NV ? (step % 3) * KSV + step / 3 : 3 * KSV + (step - NV);
     return buf_load<T>(rf, lane_off, uint32_t((ib * KS + kg) * 64) * sz);
@@ -330,16 +348,16 @@ __device__ inline void split4(const float (&x)[4], typename Mfma16x16<H16>::v4& 
   }
 }
 
-template <int N, typename H16, int NPROD, int H, bool IL, int NFI, typename Gather, typename FluxStep,
+template <int N, typename H16, int NPROD, int H, bool IL, int NFI, int RBW, typename Gather, typename FluxStep,
           typename FluxStore>
-__device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane,
-                                  f32x4 (&acc)[MfmaShape<N>::RB][3], Gather&& gather, FluxStep&& flux_step,
+__device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane, int rb0,
+                                  f32x4 (&acc)[RBW][3], Gather&& gather, FluxStep&& flux_step,
                                   FluxStore&& flux_store) {
   using S = MfmaShape<N>;
   using X = MixedShape<N>;
   using MM = Mfma16x16<H16>;
   using v4 = typename MM::v4;
-  constexpr int Np4 = S::Np4, NF = S::NF, RB = S::RB, TS = S::TS, TQ = S::TQ;
+  constexpr int Np4 = S::Np4, NF = S::NF, RB = RBW, TS = S::TS, TQ = S::TQ;
   constexpr int SV = X::SV, SL = X::SL, ST = X::ST;
   const int e = lane & 15, q = lane >> 4;
   const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag16, uint32_t(X::frag_bytes));
@@ -352,7 +370,7 @@ __device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const
   constexpr int kPre = 2;
   using FS = FluxSchedule<SV, NFI, kPre>;
   auto frag_of = [&](int step, int ib, v4& hi, v4& lo) {
-    const uint32_t off = uint32_t(((ib * ST + step) * 64 + lane) * 16);
+    const uint32_t off = uint32_t((((rb0 + ib) * ST + step) * 64 + lane) * 16);
     const auto w = __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 0, 0);
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     hi = __builtin_bit_cast(v4, u32x2{w[0], w[1]});
@@ -477,8 +495,8 @@ constexpr bool lift_split() {
   return MIX == 0 && sizeof(T) == 8 && N == 4;
 }
 
-// Workgroup = two waves sharing one tile of 16 elements; wave h = 0 produces
-// the E equations, wave h = 1 the H equations (see mfma_wave).
+// Workgroup = two or four waves sharing one tile of 16 elements; wave role
+// h = 0 produces the E equations, h = 1 the H equations (see mfma_wave).
 // MIX = 0: contraction in T on 16x16x4 MFMAs; MIX = 1..3: T = float with the
 // contraction split in BF16 (NPROD = MIX); MIX = 4..6: split in FP16
 // (NPROD = MIX - 3).
@@ -489,12 +507,17 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   using acc_t = typename M::acc;
   constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, TS = S::TS, TQ = S::TQ;
   constexpr bool LIFT_HALF = lift_split<N, T, MIX>();
+  constexpr int WPT = waves_per_tile<N, T, MIX>();
+  constexpr int NT = 64 * WPT;        // lanes per tile
+  constexpr int RBW = RB * 2 / WPT;   // row blocks per wave
   __shared__ MfmaTile<N, T, LIFT_HALF> t;
 
   const int64_t fs = a.fs;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int h = tid >> 6;
+  const int h = (tid >> 6) & 1;       // 0: E equations, 1: H equations
+  const int rh = tid >> 7;            // row-block half (four waves per tile)
+  const int rb0 = rh * RBW;
   const int e = lane & 15, q = lane >> 4;
   const int64_t k0 = tile * 16;
   const int ne = int((a.K - k0) < 16 ? (a.K - k0) : 16);
@@ -532,26 +555,26 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   // Tables: fully unrolled, 16-byte loads for the orientation table (its
   // device copy is padded to a multiple of 16 bytes), so every load is in
   // flight at once.
-  constexpr int kFmaskIters = (NF + 127) / 128;
+  constexpr int kFmaskIters = (NF + NT - 1) / NT;
 #pragma unroll
   for (int it = 0; it < kFmaskIters; ++it) {
-    const int i = tid + 128 * it;
+    const int i = tid + NT * it;
     if (i < NF) t.fmask[i] = int16_t(a.fmask[i]);
   }
   constexpr int kNbrVec = (4 * 24 * Nfp + 15) / 16;
-  constexpr int kNbrIters = (kNbrVec + 127) / 128;
+  constexpr int kNbrIters = (kNbrVec + NT - 1) / NT;
 #pragma unroll
   for (int it = 0; it < kNbrIters; ++it) {
-    const int i = tid + 128 * it;
+    const int i = tid + NT * it;
     if (i < kNbrVec) reinterpret_cast<uint4*>(t.nbr)[i] = reinterpret_cast<const uint4*>(a.nbr)[i];
   }
 
   // Fields of the tile -> LDS [c][j][e] (global reads contiguous per field).
-  constexpr int kLoadIters = (16 * Np + 127) / 128;
+  constexpr int kLoadIters = (16 * Np + NT - 1) / NT;
   T tv[kLoadIters][6];
 #pragma unroll
   for (int it = 0; it < kLoadIters; ++it) {
-    const int idx = tid + 128 * it;
+    const int idx = tid + NT * it;
     const bool in = idx < ne * Np;
     const uint32_t vo = in ? uint32_t(k0 * Np + idx) * sz : kOob;
 #pragma unroll
@@ -559,7 +582,7 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   }
 #pragma unroll
   for (int it = 0; it < kLoadIters; ++it) {
-    const int idx = tid + 128 * it;
+    const int idx = tid + NT * it;
     const int ee = idx / Np, j = idx - ee * Np;
     if (idx < 16 * Np) {
 #pragma unroll
@@ -567,26 +590,26 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
     }
   }
   if constexpr (Np4 > Np) {
-    for (int idx = tid; idx < 6 * (Np4 - Np) * 16; idx += 128) {
+    for (int idx = tid; idx < 6 * (Np4 - Np) * 16; idx += NT) {
       const int c = idx / ((Np4 - Np) * 16), r = idx - c * ((Np4 - Np) * 16);
       t.su[(c * Np4 + Np + r / 16) * TS + (r & 15)] = T(0);
     }
   }
   __syncthreads();
 
-  // Flux phase, run by all 128 lanes between the volume and the lift phases:
+  // Flux phase, run by all lanes of the tile between the volume and the lift phases:
   // one lane per (element, face node) pair, each flux evaluated once.  All
   // exterior traces of a lane are gathered at once; own traces are read from
   // the field tile, which is then overwritten by the fluxes [c][m][e].
   constexpr int kPairs = 16 * NF;
-  constexpr int kFluxIters = (kPairs + 127) / 128;
+  constexpr int kFluxIters = (kPairs + NT - 1) / NT;
   const T alpha = T(a.alpha);
   T gx[kFluxIters][6];
   T fl[kFluxIters][6];
   auto gather = [&]() {
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
-      const int pr = tid + 128 * it;
+      const int pr = tid + NT * it;
       const int ee = pr & 15, m = pr >> 4;
       const int f = m / Nfp, jj = m - f * Nfp;
       const int32_t cf = (pr < kPairs) ? t.code[4 * ee + f] : -1;
@@ -600,7 +623,7 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
     }
   };
   auto flux_step = [&](int it) {
-    const int pr = tid + 128 * it;
+    const int pr = tid + NT * it;
     const int ee = pr & 15, m = pr >> 4;
     if (pr < kPairs) {
       const int f = m / Nfp;
@@ -636,7 +659,7 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
     const int base = part == 1 ? S::HB : 0;
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
-      const int pr = tid + 128 * it;
+      const int pr = tid + NT * it;
       const int ee = pr & 15, m = pr >> 4;
       if (it >= it0 && it < it1 && pr < kPairs) {
 #pragma unroll
@@ -646,44 +669,48 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   };
 
   constexpr bool IL = flux_interleaved<N, T, MIX>();
-  acc_t acc[RB][3];
+  static_assert(WPT == 2 || (!IL && !LIFT_HALF), "interleaved flux and split lift assume 128 lanes per tile");
+  acc_t acc[RBW][3];
   if constexpr (MIX == 0) {
     if (h == 0)
-      mfma_wave<N, T, 0, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
+      mfma_wave<N, T, 0, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
     else
-      mfma_wave<N, T, 1, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
+      mfma_wave<N, T, 1, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
   } else {
     using H16 = typename std::conditional<(MIX <= 3), __bf16, _Float16>::type;
     constexpr int NPROD = MIX <= 3 ? MIX : MIX - 3;
     if (h == 0)
-      mixed_wave<N, H16, NPROD, 0, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
+      mixed_wave<N, H16, NPROD, 0, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
     else
-      mixed_wave<N, H16, NPROD, 1, IL, kFluxIters>(a, t, mr, lane, acc, gather, flux_step, flux_store);
+      mixed_wave<N, H16, NPROD, 1, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
   }
 
-  // Epilogue through LDS: [c][e][i] for this wave's three fields, then
-  // contiguous stores per field.
+  // Epilogue through LDS: [c][e][i] for the role's three fields (the waves
+  // of one role fill disjoint row blocks), then contiguous stores per field,
+  // shared by the WPT / 2 waves of the role.
   __syncthreads();
   T* so = t.su + h * (3 * 16 * Np);
 #pragma unroll
-  for (int ib = 0; ib < RB; ++ib)
+  for (int ib = 0; ib < RBW; ++ib)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * ib + M::row(q, r);
+        const int i = 16 * (rb0 + ib) + M::row(q, r);
         if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
       }
   __syncthreads();
   const int nv = ne * Np;
-  constexpr int kOutIters = (16 * Np + 63) / 64;
+  constexpr int kRoleLanes = 64 * (WPT / 2);
+  const int rl = lane + 64 * rh;      // lane within the role
+  constexpr int kOutIters = (16 * Np + kRoleLanes - 1) / kRoleLanes;
   if constexpr (!RK) {
     T* __restrict__ rhs = static_cast<T*>(a.rhs);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int it = 0; it < kOutIters; ++it) {
-        const int idx = lane + 64 * it;
+        const int idx = rl + kRoleLanes * it;
         if (idx < nv) rhs[(3 * h + c) * fs + k0 * Np + idx] = so[c * 16 * Np + idx];
       }
   } else {
@@ -696,7 +723,7 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
       T rv[kOutIters], uv[kOutIters];
 #pragma unroll
       for (int it = 0; it < kOutIters; ++it) {
-        const int idx = lane + 64 * it;
+        const int idx = rl + kRoleLanes * it;
         const uint32_t vo = idx < nv ? uint32_t(k0 * Np + idx) * sz : kOob;
         const uint32_t so_ = uint32_t((3 * h + c) * fs) * sz;
         rv[it] = buf_load<T>(rr, vo, so_);
@@ -704,7 +731,7 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
       }
 #pragma unroll
       for (int it = 0; it < kOutIters; ++it) {
-        const int idx = lane + 64 * it;
+        const int idx = rl + kRoleLanes * it;
         if (idx < nv) {
           const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
           const T r = ra * rv[it] + dt * so[c * 16 * Np + idx];
@@ -724,7 +751,7 @@ __device__ inline int64_t xcd_tile(int64_t n) {
 }
 
 template <int N, typename T, bool RK, int MIX>
-__global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
+__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>())) void rhs_mfma_kernel(RhsArgs a) {
   const int64_t tile = xcd_tile((a.K + 15) / 16);
   if (tile >= (a.K + 15) / 16) return;
   rhs_mfma_tile<N, T, RK, MIX>(a, tile);
@@ -735,7 +762,7 @@ __global__ __launch_bounds__(128) void rhs_mfma_kernel(RhsArgs a) {
 // pointers come from the descriptor table.  parity 0 reads u and writes the
 // second state buffer, parity 1 the reverse.
 template <int N, typename T, int MIX>
-__global__ __launch_bounds__(128) void rk_mfma_batch_kernel(BatchArgs b) {
+__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>())) void rk_mfma_batch_kernel(BatchArgs b) {
   const int64_t item = xcd_tile(b.n_items);
   if (item >= b.n_items) return;
   const int2 w = b.items[item];
@@ -764,7 +791,7 @@ __global__ __launch_bounds__(128) void rk_mfma_batch_kernel(BatchArgs b) {
 template <int N, typename T, int MIX = 0>
 hipError_t launch_rk_mfma_batch(const BatchArgs& b, hipStream_t s) {
   const unsigned grid = unsigned(8 * ((b.n_items + 7) / 8));
-  hipLaunchKernelGGL((rk_mfma_batch_kernel<N, T, MIX>), dim3(grid), dim3(128), 0, s, b);
+  hipLaunchKernelGGL((rk_mfma_batch_kernel<N, T, MIX>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s, b);
   return hipGetLastError();
 }
 
@@ -772,7 +799,7 @@ template <int N, typename T, int MIX = 0>
 hipError_t launch_rhs_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false, MIX>), dim3(grid), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false, MIX>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s, a);
   return hipGetLastError();
 }
 
@@ -780,7 +807,7 @@ template <int N, typename T, int MIX = 0>
 hipError_t launch_rk_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true, MIX>), dim3(grid), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true, MIX>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s, a);
   return hipGetLastError();
 }
 
