@@ -4,14 +4,16 @@
 Workload (default): the 24^3 x 6 jittered Kuhn cube (K = 82,944 tetrahedra),
 order N = 4 (Np = 35), perfectly conducting walls, upwind flux, fields = the
 (1,1,0) cavity mode plus seeded N(0, 1e-3) noise.  One "step" is one LSERK
-time step: five right-hand-side evaluations and five stage updates over the
-whole mesh (dg_rk_step with nsteps = 1).
+time step: five right-hand-side evaluations, each fused with its stage
+update, over the whole mesh; the K timed steps are one dg_rk_step call.
 
 Metric: GDOF/s per RHS evaluation = 5 * 6 * K * Np * steps / time / 1e9,
 inputs resident in HBM, timed with HIP events on the stream the library
-launches on.  The "roofline" object describes the dominant kernel (the fused
-right-hand side) from its algorithmic flop count and its average launch time
-measured here; "cpu_baseline" times the FP64 CPU oracle on a bounded sample.
+launches on.  The "roofline" object describes the dominant kernel, the fused
+stage (right-hand side + update), from its algorithmic flop and byte counts
+and its average launch time over the timed region (time / (5 steps));
+"rhs_only" gives the same for the plain right-hand side timed by dg_time_rhs.
+"cpu_baseline" times the FP64 CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -37,13 +39,14 @@ PEAKS = {  # MI355X published peaks (dense)
 }
 
 
-def flops_per_element(N: int) -> int:
+def flops_per_element(N: int, stage: bool = False) -> int:
     """Algorithmic flops of one RHS per element: 18 Np x Np matvecs (Dr, Ds,
     Dt of six fields), 6 Np x 4Nfp matvecs (LIFT), the upwind flux (~60 per
-    face node) and metric + curl (~66 per node)."""
+    face node) and metric + curl (~66 per node).  A fused LSERK stage adds the
+    update res = a res + dt rhs, u' = u + b res: 5 flops per value."""
     Np = (N + 1) * (N + 2) * (N + 3) // 6
     Nfp = (N + 1) * (N + 2) // 2
-    return 36 * Np * Np + 48 * Np * Nfp + 240 * Nfp + 66 * Np
+    return 36 * Np * Np + 48 * Np * Nfp + 240 * Nfp + 66 * Np + (30 * Np if stage else 0)
 
 
 def contraction_flops_per_element(N: int) -> int:
@@ -53,11 +56,13 @@ def contraction_flops_per_element(N: int) -> int:
     return 36 * Np * Np + 48 * Np * Nfp
 
 
-def bytes_per_element(N: int, s: int) -> int:
+def bytes_per_element(N: int, s: int, stage: bool = False) -> int:
     """Algorithmic HBM bytes of one RHS per element: read u, write rhs
-    (6 Np scalars each), 25 geometry scalars, 16 bytes of connectivity."""
+    (6 Np scalars each), 25 geometry scalars, 16 bytes of connectivity.  A
+    fused LSERK stage reads u and res and writes res and the new state: four
+    state arrays instead of two."""
     Np = (N + 1) * (N + 2) * (N + 3) // 6
-    return 2 * 6 * Np * s + 25 * s + 16
+    return (4 if stage else 2) * 6 * Np * s + 25 * s + 16
 
 
 def make_problem(dg, k, N, precision):
@@ -104,17 +109,21 @@ def cpu_baseline(VX, EToV, N, budget_s=20.0):
                       f"(mean {t:.2f} s each); host has {os.cpu_count()} logical CPUs"}
 
 
-def roofline(prec, N, K, t_rhs, s):
-    """(bound, achieved, peak, unit) of one RHS of K elements taking t_rhs s."""
-    flops = flops_per_element(N) * K
+def roofline(prec, N, K, t_rhs, s, stage=False):
+    """(bound, achieved, peak, unit) of one RHS (or fused LSERK stage) of K
+    elements taking t_rhs s.  FP64/FP32 are priced against the matrix-core
+    peak of their dtype; the split precisions against whichever of HBM bytes
+    and 16-bit matrix-core work takes longer."""
+    flops = flops_per_element(N, stage) * K
     if prec in ("fp64", "fp32"):
         peak = PEAKS["fp64_TFs"] if prec == "fp64" else PEAKS["fp32_TFs"]
         return "mfma", flops / t_rhs / 1e12, peak, "TFLOP/s"
     nprod = int(prec[-1]) if prec[-1].isdigit() else 1
-    t_hbm = bytes_per_element(N, s) * K / (PEAKS["hbm_GBs"] * 1e9)
+    nbytes = bytes_per_element(N, s, stage) * K
+    t_hbm = nbytes / (PEAKS["hbm_GBs"] * 1e9)
     t_mma = nprod * contraction_flops_per_element(N) * K / (PEAKS["bf16_TFs"] * 1e12)
     if t_hbm >= t_mma:
-        return "hbm", bytes_per_element(N, s) * K / t_rhs / 1e9, PEAKS["hbm_GBs"], "GB/s"
+        return "hbm", nbytes / t_rhs / 1e9, PEAKS["hbm_GBs"], "GB/s"
     return "mfma", nprod * contraction_flops_per_element(N) * K / t_rhs / 1e12, PEAKS["bf16_TFs"], "TFLOP/s"
 
 
@@ -287,50 +296,50 @@ def main():
         dt = 0.5 * p.info.dt_cfl1
         stream = torch.cuda.current_stream()
         t_rhs = time_rhs(torch, p, du, out, args.rhs_reps)
+        # Warm-up and timed region: one dg_rk_step call each.  The fused
+        # stages ping-pong between two state buffers, so a call of n steps
+        # (5 n stages) needs a state copy at the end only when n is odd.
         p.rk_step(du, res, 0.0, dt, args.warmup, stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        for _ in range(args.steps):
-            p.rk_step(du, res, 0.0, dt, 1, stream)
+        p.rk_step(du, res, 0.0, dt, args.steps, stream)
         e1.record(stream)
         e1.synchronize()
         torch.cuda.synchronize()
         t_total = e0.elapsed_time(e1) / 1e3
+        t_stage = t_total / (5 * args.steps)   # average fused-stage launch in the timed region
         dofs = 6 * K * Np
-        flops = flops_per_element(N) * K
-        peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"]}.get(prec, PEAKS["bf16_TFs"])
-        achieved = flops / t_rhs / 1e12
         tname = "double" if prec == "fp64" else "float"
         mix = {"fp64": 0, "fp32": 0, "bf16": 1, "bf16x2": 2, "bf16x3": 3, "f16": 4, "f16x2": 5, "f16x3": 6}[prec]
-        kname = (f"void dgd::rhs_mfma_kernel<{N}, {tname}, false, {mix}>(dgd::RhsArgs)" if p.variant == "mfma"
-                 else f"void dgd::rhs_valu_kernel<{N}, {tname}>(dgd::RhsArgs)")
-        traffic = profiling.read_traffic(traffic_file, kname)
-        # Split precisions: the contractions run at the 16-bit matrix-core rate,
-        # so the bound is whichever of HBM bytes and MFMA work is slower.
-        if prec not in ("fp64", "fp32"):
-            nprod = mix if mix <= 3 else mix - 3
-            t_hbm = bytes_per_element(N, s) * K / (PEAKS["hbm_GBs"] * 1e9)
-            t_mma = nprod * contraction_flops_per_element(N) * K / (PEAKS["bf16_TFs"] * 1e12)
-            if t_hbm >= t_mma:
-                bound, achieved, peak, unit = "hbm", bytes_per_element(N, s) * K / t_rhs / 1e9, PEAKS["hbm_GBs"], "GB/s"
-            else:
-                bound, achieved, peak, unit = "mfma", nprod * contraction_flops_per_element(N) * K / t_rhs / 1e12, \
-                    PEAKS["bf16_TFs"], "TFLOP/s"
+        if p.variant == "mfma":
+            kname = f"void dgd::rhs_mfma_kernel<{N}, {tname}, true, {mix}>(dgd::RhsArgs)"
+            kname_rhs = f"void dgd::rhs_mfma_kernel<{N}, {tname}, false, {mix}>(dgd::RhsArgs)"
         else:
-            bound, unit = ("mfma" if p.variant == "mfma" else "alu"), "TFLOP/s"
+            kname = kname_rhs = f"void dgd::rhs_valu_kernel<{N}, {tname}>(dgd::RhsArgs)"
+        traffic = profiling.read_traffic(traffic_file, kname)
+        bound, achieved, peak, unit = roofline(prec, N, K, t_stage, s, stage=True)
+        if prec in ("fp64", "fp32") and p.variant != "mfma":
+            bound = "alu"
+        rb, ra, rp, ru = roofline(prec, N, K, t_rhs, s)
         results[prec] = {
             "value": 5 * dofs * args.steps / t_total / 1e9,
             "ms_per_step": 1e3 * t_total / args.steps,
+            "stage_us": 1e6 * t_stage,
             "rhs_us": 1e6 * t_rhs,
             "rhs_gdofs": dofs / t_rhs / 1e9,
             "roofline": {"bound": bound, "achieved": achieved, "peak": peak,
                          "unit": unit, "frac": achieved / peak, "traffic": traffic,
                          "kernel": kname,
-                         "algorithmic_flops_per_launch": flops,
-                         "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K,
-                         "hbm_GBs_algorithmic": bytes_per_element(N, s) * K / t_rhs / 1e9},
+                         "launch_us": 1e6 * t_stage,
+                         "algorithmic_flops_per_launch": flops_per_element(N, True) * K,
+                         "algorithmic_bytes_per_launch": bytes_per_element(N, s, True) * K,
+                         "hbm_GBs_algorithmic": bytes_per_element(N, s, True) * K / t_stage / 1e9},
+            "rhs_only": {"kernel": kname_rhs, "launch_us": 1e6 * t_rhs, "bound": rb, "achieved": ra,
+                         "peak": rp, "unit": ru, "frac": ra / rp,
+                         "traffic": profiling.read_traffic(traffic_file, kname_rhs),
+                         "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K},
             "K": K, "Np": Np, "variant": p.variant,
         }
         p.close()
@@ -356,8 +365,10 @@ def main():
         "roofline": main_r["roofline"],
         "rhs_us": main_r["rhs_us"],
         "rhs_gdofs": main_r["rhs_gdofs"],
-        "other_precision": {o: {kk: results[o][kk] for kk in ("value", "ms_per_step", "rhs_us", "rhs_gdofs", "roofline",
-                                                             "variant")} for o in others},
+        "stage_us": main_r["stage_us"],
+        "rhs_only": main_r["rhs_only"],
+        "other_precision": {o: {kk: results[o][kk] for kk in ("value", "ms_per_step", "stage_us", "rhs_us", "rhs_gdofs",
+                                                             "roofline", "rhs_only", "variant")} for o in others},
     }
     if not args.no_cpu_baseline:
         VX, EToV = I.kuhn_cube(k, 0.1, 0)

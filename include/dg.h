@@ -112,7 +112,9 @@ typedef struct {
  * the current HIP device.  Synchronous.  *out receives a new handle on
  * success and is left untouched on error.
  * Errors: DG_EINVAL (null pointer, K or Nv < 1, alpha not finite, precision
- * out of range), DG_EUNSUPPORTED (N outside 1..9, K too large), DG_EMESH
+ * out of range), DG_EUNSUPPORTED (N outside 1..9, K >= 2^26, or one state
+ * array -- 6 fields of K * Np values, each padded to 256 bytes -- of 2 GiB or
+ * more: the kernels use 32-bit buffer offsets), DG_EMESH
  * (vertex id out of range, J <= 0, face multiplicity > 2), DG_EHIP/DG_ENOMEM. */
 dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out);
 

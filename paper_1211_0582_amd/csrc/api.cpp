@@ -306,6 +306,14 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   if (st != DG_OK) return st;
   const RefElement* re = ref_element(desc->N);
   if (!re) return fail(DG_EUNSUPPORTED, "reference element construction failed");
+  {
+    // The kernels address a state array with 32-bit buffer offsets and use
+    // offset 2^31 as the "reads zero" sentinel, so an array must stay below it.
+    const int64_t eb = desc->precision == DG_FP64 ? 8 : 4;
+    const int64_t fs = ((desc->K * re->Np + 256 / eb - 1) / (256 / eb)) * (256 / eb);
+    if (6 * fs * eb >= (int64_t(1) << 31))
+      return fail(DG_EUNSUPPORTED, "state array of 2 GiB or more (K * Np too large for this precision)");
+  }
 
   auto p = new dg_problem_s();
   p->N = desc->N;

@@ -179,7 +179,7 @@ struct FluxSchedule {
 // (all RB blocks with two waves per tile, half of them with four).
 template <int N, typename T, int H, bool IL, int NFI, int RBW, typename Tile, typename Gather, typename FluxStep,
           typename FluxStore>
-__device__ inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], int lane, int rb0,
+__device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], int lane, int rb0,
                                  typename Mfma16<T>::acc (&acc)[RBW][3], Gather&& gather,
                                  FluxStep&& flux_step, FluxStore&& flux_store) {
   using S = MfmaShape<N>;
@@ -350,7 +350,7 @@ __device__ inline void split4(const float (&x)[4], typename Mfma16x16<H16>::v4& 
 
 template <int N, typename H16, int NPROD, int H, bool IL, int NFI, int RBW, typename Gather, typename FluxStep,
           typename FluxStore>
-__device__ inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane, int rb0,
+__device__ __attribute__((always_inline)) inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane, int rb0,
                                   f32x4 (&acc)[RBW][3], Gather&& gather, FluxStep&& flux_step,
                                   FluxStore&& flux_store) {
   using S = MfmaShape<N>;
@@ -501,7 +501,7 @@ constexpr bool lift_split() {
 // contraction split in BF16 (NPROD = MIX); MIX = 4..6: split in FP16
 // (NPROD = MIX - 3).
 template <int N, typename T, bool RK, int MIX>
-__device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
+__device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
@@ -688,6 +688,30 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   // Epilogue through LDS: [c][e][i] for the role's three fields (the waves
   // of one role fill disjoint row blocks), then contiguous stores per field,
   // shared by the WPT / 2 waves of the role.
+  const int nv = ne * Np;
+  constexpr int kRoleLanes = 64 * (WPT / 2);
+  const int rl = lane + 64 * rh;      // lane within the role
+  constexpr int kOutIters = (16 * Np + kRoleLanes - 1) / kRoleLanes;
+  // Runge-Kutta stage: the residual and state loads of the update are issued
+  // before the accumulators go through LDS, up to kAhead (component, slot)
+  // items at a time, so their latency overlaps the exchange and the stores of
+  // earlier items.  The field offset depends on the role (a per-lane value to
+  // the compiler), so it goes into the vector offset: a per-lane scalar
+  // offset would make every load a waterfall loop.
+  constexpr int kItems = 3 * kOutIters;
+  constexpr int kAheadRegs = sizeof(T) == 8 ? 112 : 48;  // VGPRs given to loads in flight
+  constexpr int kAhead = RK ? (kItems * 2 * int(sz / 4) <= kAheadRegs ? kItems : kAheadRegs / (2 * int(sz / 4))) : 0;
+  T rv[RK ? kItems : 1], uv[RK ? kItems : 1];
+  const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.res, RK ? 6u * uint32_t(fs) * sz : 0u);
+  auto rk_load = [&](int j) {
+    const int c = j / kOutIters, it = j % kOutIters;
+    const int idx = rl + kRoleLanes * it;
+    const uint32_t vo = idx < nv ? uint32_t((3 * h + c) * fs + k0 * Np + idx) * sz : kOob;
+    rv[j] = buf_load<T>(rr, vo, 0);
+    uv[j] = buf_load<T>(ru, vo, 0);
+  };
+#pragma unroll
+  for (int j = 0; j < kAhead; ++j) rk_load(j);
   __syncthreads();
   T* so = t.su + h * (3 * 16 * Np);
 #pragma unroll
@@ -700,10 +724,6 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
         if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
       }
   __syncthreads();
-  const int nv = ne * Np;
-  constexpr int kRoleLanes = 64 * (WPT / 2);
-  const int rl = lane + 64 * rh;      // lane within the role
-  constexpr int kOutIters = (16 * Np + kRoleLanes - 1) / kRoleLanes;
   if constexpr (!RK) {
     T* __restrict__ rhs = static_cast<T*>(a.rhs);
 #pragma unroll
@@ -716,28 +736,17 @@ __device__ inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   } else {
     T* __restrict__ res = static_cast<T*>(a.res);
     T* __restrict__ uo = static_cast<T*>(a.u_out);
-    const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.res, 6u * uint32_t(fs) * sz);
     const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T rv[kOutIters], uv[kOutIters];
-#pragma unroll
-      for (int it = 0; it < kOutIters; ++it) {
-        const int idx = rl + kRoleLanes * it;
-        const uint32_t vo = idx < nv ? uint32_t(k0 * Np + idx) * sz : kOob;
-        const uint32_t so_ = uint32_t((3 * h + c) * fs) * sz;
-        rv[it] = buf_load<T>(rr, vo, so_);
-        uv[it] = buf_load<T>(ru, vo, so_);
-      }
-#pragma unroll
-      for (int it = 0; it < kOutIters; ++it) {
-        const int idx = rl + kRoleLanes * it;
-        if (idx < nv) {
-          const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
-          const T r = ra * rv[it] + dt * so[c * 16 * Np + idx];
-          res[g] = r;
-          uo[g] = uv[it] + rb * r;
-        }
+    for (int j = 0; j < kItems; ++j) {
+      if (j + kAhead < kItems) rk_load(j + kAhead);
+      const int c = j / kOutIters, it = j % kOutIters;
+      const int idx = rl + kRoleLanes * it;
+      if (idx < nv) {
+        const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
+        const T r = ra * rv[j] + dt * so[c * 16 * Np + idx];
+        res[g] = r;
+        uo[g] = uv[j] + rb * r;
       }
     }
   }

@@ -406,10 +406,12 @@ __global__ __launch_bounds__(128 * TPW) void rhs_mfma_p_kernel(RhsArgs a, int pe
 #pragma unroll
         for (int oi = 0; oi < kOutIters; ++oi) {
           const int idx = lane + 64 * oi;
-          const uint32_t vo = idx < nv ? uint32_t(k0 * Np + idx) * sz : kOob;
-          const uint32_t so_ = uint32_t((3 * h + c) * fs) * sz;
-          rv[oi] = buf_load<T>(rr, vo, so_);
-          uv[oi] = buf_load<T>(ru, vo, so_);
+          // The field offset depends on the role (a per-lane value to the
+          // compiler), so it goes into the vector offset: a per-lane scalar
+          // offset would make every load a waterfall loop.
+          const uint32_t vo = idx < nv ? uint32_t((3 * h + c) * fs + k0 * Np + idx) * sz : kOob;
+          rv[oi] = buf_load<T>(rr, vo, 0);
+          uv[oi] = buf_load<T>(ru, vo, 0);
         }
 #pragma unroll
         for (int oi = 0; oi < kOutIters; ++oi) {

@@ -106,3 +106,13 @@ def test_null_arguments_rejected():
     assert dg.lib.dg_info_get(None, None) == dg.DG_EINVAL
     assert dg.lib.dg_setup_mesh(None, None) == dg.DG_EINVAL
     dg.lib.dg_destroy(None)
+
+
+def test_setup_rejects_state_arrays_beyond_buffer_offsets():
+    # N = 9 (Np = 220) on 6 * 33^3 = 215,622 tets: one FP64 state array is
+    # 6 * 47.4e6 * 8 B = 2.28 GB, past the 2^31-byte range of the kernels'
+    # 32-bit buffer offsets, so setup must refuse it before any device work.
+    VX, EToV = I.kuhn_cube(33, 0.0, 0)
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(9, VX, EToV, precision=dg.DG_FP64)
+    assert e.value.status == dg.DG_EUNSUPPORTED and "2 GiB" in str(e.value)
