@@ -159,6 +159,10 @@ dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, in
  * t is the start time; the perfectly conducting cavity has no time-dependent
  * data, so the stage times t + C_s dt do not enter the arithmetic.
  * Uses library-owned scratch allocated at setup; asynchronous on stream.
+ * Where the fused stage kernel exists, each stage reads one state buffer
+ * (u or the scratch) and writes the other, so a call whose 5 * nsteps stages
+ * are odd in number ends with one device copy of the state back into u:
+ * step many times per call rather than once per call.
  * Errors: DG_EINVAL (null pointer, u == res, nsteps < 0, dt not finite). */
 dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
                      int32_t nsteps, void* stream);
