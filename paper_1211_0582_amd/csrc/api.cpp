@@ -229,6 +229,8 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   a.res = nullptr;
   a.u_out = nullptr;
   a.rk_a = a.rk_b = a.rk_dt = 0.0;
+  // u read, rhs written.
+  a.stream_out = 2 * p->state_elems * p->elem_bytes > kLastLevelCacheBytes;
   return a;
 }
 
@@ -449,6 +451,8 @@ dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int3
     void* nxt = p->d_scratch;
     ra.res = res;
     ra.rk_dt = dt;
+    // u and res read, res and the other state buffer written.
+    ra.stream_out = 3 * p->state_elems * p->elem_bytes > kLastLevelCacheBytes;
     for (int32_t n = 0; n < nsteps; ++n)
       for (int st = 0; st < 5; ++st) {
         ra.u = cur;

@@ -41,6 +41,7 @@ struct dg_batch_s {
   bool table_valid = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // step starting at parity 0 / 1
   int precision = 0;
+  int stream_out = 0;  // streaming stores: the step's state arrays exceed the last-level cache
 };
 
 namespace {
@@ -80,6 +81,7 @@ dg_status launch_step(dg_batch b, int parity0, hipStream_t s) {
       a.parity = (parity0 + st) & 1;
       a.rk_a = kRkA[st];
       a.rk_b = kRkB[st];
+      a.stream_out = b->stream_out;
       hipError_t e = g.launch(a, s);
       if (e != hipSuccess) return hip_err(e, "batched stage launch");
     }
@@ -141,6 +143,10 @@ dg_status dg_setup_batch(int32_t n, const dg_mesh_desc* descs, dg_batch* out) {
     }
     b->problems.push_back(p);
   }
+  // One step cycles through every problem's u, res and second state buffer.
+  int64_t step_bytes = 0;
+  for (dg_problem p : b->problems) step_bytes += 3 * p->state_elems * p->elem_bytes;
+  b->stream_out = step_bytes > kLastLevelCacheBytes;
   std::map<int, std::vector<int2>> items;
   for (int32_t i = 0; i < n; ++i) {
     dg_problem p = b->problems[i];

@@ -30,6 +30,7 @@ struct RhsArgs {
   void* res;
   void* u_out;
   double rk_a, rk_b, rk_dt;
+  int32_t stream_out;     // 1: FP64 outputs written with non-temporal (streaming) stores
 };
 
 // One problem of a batch (device descriptor table entry).
@@ -54,6 +55,7 @@ struct BatchArgs {
   const int32_t* fmask;
   int parity;
   double rk_a, rk_b;
+  int32_t stream_out;     // 1: outputs written with non-temporal (streaming) stores
 };
 using BatchLauncher = hipError_t (*)(const BatchArgs&, hipStream_t);
 

@@ -29,5 +29,10 @@ struct dg_problem_s {
 extern const double kRkA[5];
 extern const double kRkB[5];
 
+// Last-level cache of the device (MI355X: 256 MB Infinity Cache).  An FP64
+// launch whose arrays exceed it writes its outputs with streaming stores: they
+// could not stay resident for the next launch, and such stores retire sooner.
+constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;
+
 // Kernel arguments of a right-hand-side evaluation of p.
 dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs);
