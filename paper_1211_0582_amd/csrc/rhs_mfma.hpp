@@ -533,43 +533,47 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.conn, uint32_t(a.K) * 4 * 4);
   const __amdgpu_buffer_rsrc_t ru = make_rsrc(a.u, 6u * uint32_t(fs) * sz);
 
-  // Metric of this lane's element in registers; face records and tables in LDS.
+  // Every global load of the prologue is issued before the first LDS write:
+  // a write needs its data, and a load issued after such a wait (or in a
+  // later branch) would add a full memory round trip to the prologue.
+  // Metric of this lane's element in registers.
   T mr[9];
   {
     const uint32_t go = live ? uint32_t(ke * kGeoStride) * sz : kOob;
 #pragma unroll
     for (int i = 0; i < 9; ++i) mr[i] = buf_load<T>(rg, go, i * sz);
   }
-  if (tid < 64) {
-    const int ee = tid >> 2, f = tid & 3;  // 16 elements x 4 faces
-    const bool lv = ee < ne;
+  // Face records and connectivity codes (lanes 0..63: 16 elements x 4 faces).
+  T fc[4];
+  int32_t cf;
+  {
+    const int ee = (tid >> 2) & 15, f = tid & 3;
+    const bool lv = tid < 64 && ee < ne;
     const uint32_t go = lv ? uint32_t((k0 + ee) * kGeoStride + 9 + 4 * f) * sz : kOob;
-    const int32_t cf = __builtin_bit_cast(int32_t, __builtin_amdgcn_raw_buffer_load_b32(
-                                                       rc, lv ? uint32_t((k0 + ee) * 4 + f) * 4 : kOob, 0, 0));
-    t.code[tid] = lv ? cf : -1;
-    t.face[4 * tid + 0] = buf_load<T>(rg, go, 0);
-    t.face[4 * tid + 1] = buf_load<T>(rg, go, sz);
-    t.face[4 * tid + 2] = buf_load<T>(rg, go, 2 * sz);
-    t.face[4 * tid + 3] = T(0.5) * buf_load<T>(rg, go, 3 * sz);
+    cf = __builtin_bit_cast(int32_t, __builtin_amdgcn_raw_buffer_load_b32(
+                                         rc, lv ? uint32_t((k0 + ee) * 4 + f) * 4 : kOob, 0, 0));
+    cf = lv ? cf : -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fc[i] = buf_load<T>(rg, go, i * sz);
   }
-  // Tables: fully unrolled, 16-byte loads for the orientation table (its
-  // device copy is padded to a multiple of 16 bytes), so every load is in
-  // flight at once.
+  // Tables (indices clamped so the loads need no branch); 16-byte loads for
+  // the orientation table (its device copy is padded to a multiple of 16 B).
   constexpr int kFmaskIters = (NF + NT - 1) / NT;
+  int32_t fmv[kFmaskIters];
 #pragma unroll
   for (int it = 0; it < kFmaskIters; ++it) {
     const int i = tid + NT * it;
-    if (i < NF) t.fmask[i] = int16_t(a.fmask[i]);
+    fmv[it] = a.fmask[i < NF ? i : NF - 1];
   }
   constexpr int kNbrVec = (4 * 24 * Nfp + 15) / 16;
   constexpr int kNbrIters = (kNbrVec + NT - 1) / NT;
+  uint4 nbv[kNbrIters];
 #pragma unroll
   for (int it = 0; it < kNbrIters; ++it) {
     const int i = tid + NT * it;
-    if (i < kNbrVec) reinterpret_cast<uint4*>(t.nbr)[i] = reinterpret_cast<const uint4*>(a.nbr)[i];
+    nbv[it] = reinterpret_cast<const uint4*>(a.nbr)[i < kNbrVec ? i : kNbrVec - 1];
   }
-
-  // Fields of the tile -> LDS [c][j][e] (global reads contiguous per field).
+  // Fields of the tile (global reads contiguous per field).
   constexpr int kLoadIters = (16 * Np + NT - 1) / NT;
   T tv[kLoadIters][6];
 #pragma unroll
@@ -579,6 +583,25 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     const uint32_t vo = in ? uint32_t(k0 * Np + idx) * sz : kOob;
 #pragma unroll
     for (int c = 0; c < 6; ++c) tv[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
+  }
+
+  // LDS: face records, codes, tables, then the fields [c][j][e].
+  if (tid < 64) {
+    t.code[tid] = cf;
+    t.face[4 * tid + 0] = fc[0];
+    t.face[4 * tid + 1] = fc[1];
+    t.face[4 * tid + 2] = fc[2];
+    t.face[4 * tid + 3] = T(0.5) * fc[3];
+  }
+#pragma unroll
+  for (int it = 0; it < kFmaskIters; ++it) {
+    const int i = tid + NT * it;
+    if (i < NF) t.fmask[i] = int16_t(fmv[it]);
+  }
+#pragma unroll
+  for (int it = 0; it < kNbrIters; ++it) {
+    const int i = tid + NT * it;
+    if (i < kNbrVec) reinterpret_cast<uint4*>(t.nbr)[i] = nbv[it];
   }
 #pragma unroll
   for (int it = 0; it < kLoadIters; ++it) {
@@ -724,6 +747,13 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
       }
   __syncthreads();
+  // Staged value (component c, slot it) of this lane, read without a branch
+  // (the index is clamped into the component's rows) so that a component's
+  // reads are issued together rather than one per store.
+  auto so_at = [&](int c, int it) {
+    const int idx = rl + kRoleLanes * it;
+    return so[c * 16 * Np + (idx < 16 * Np ? idx : 16 * Np - 1)];
+  };
   // FP64 outputs go through streaming (non-temporal) stores when the host
   // says the arrays a launch touches exceed the last-level cache: there they
   // cannot stay resident for the next launch anyway, and such stores retire
@@ -735,26 +765,36 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       if constexpr (!RK) {
         T* __restrict__ rhs = static_cast<T*>(a.rhs);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c) {
+          T ov[kOutIters];
+#pragma unroll
+          for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
 #pragma unroll
           for (int it = 0; it < kOutIters; ++it) {
             const int idx = rl + kRoleLanes * it;
-            if (idx < nv) __builtin_nontemporal_store(so[c * 16 * Np + idx], &rhs[(3 * h + c) * fs + k0 * Np + idx]);
+            if (idx < nv) __builtin_nontemporal_store(ov[it], &rhs[(3 * h + c) * fs + k0 * Np + idx]);
           }
+        }
       } else {
         T* __restrict__ res = static_cast<T*>(a.res);
         T* __restrict__ uo = static_cast<T*>(a.u_out);
         const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-          if (j + kAhead < kItems) rk_load(j + kAhead);
-          const int c = j / kOutIters, it = j % kOutIters;
-          const int idx = rl + kRoleLanes * it;
-          if (idx < nv) {
-            const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
-            const T r = ra * rv[j] + dt * so[c * 16 * Np + idx];
-            __builtin_nontemporal_store(r, &res[g]);
-            __builtin_nontemporal_store(uv[j] + rb * r, &uo[g]);
+        for (int c = 0; c < 3; ++c) {
+          T ov[kOutIters];
+#pragma unroll
+          for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
+#pragma unroll
+          for (int it = 0; it < kOutIters; ++it) {
+            const int j = c * kOutIters + it;
+            if (j + kAhead < kItems) rk_load(j + kAhead);
+            const int idx = rl + kRoleLanes * it;
+            if (idx < nv) {
+              const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
+              const T r = ra * rv[j] + dt * ov[it];
+              __builtin_nontemporal_store(r, &res[g]);
+              __builtin_nontemporal_store(uv[j] + rb * r, &uo[g]);
+            }
           }
         }
       }
@@ -764,26 +804,36 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   if constexpr (!RK) {
     T* __restrict__ rhs = static_cast<T*>(a.rhs);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+      T ov[kOutIters];
+#pragma unroll
+      for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
 #pragma unroll
       for (int it = 0; it < kOutIters; ++it) {
         const int idx = rl + kRoleLanes * it;
-        if (idx < nv) rhs[(3 * h + c) * fs + k0 * Np + idx] = so[c * 16 * Np + idx];
+        if (idx < nv) rhs[(3 * h + c) * fs + k0 * Np + idx] = ov[it];
       }
+    }
   } else {
     T* __restrict__ res = static_cast<T*>(a.res);
     T* __restrict__ uo = static_cast<T*>(a.u_out);
     const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      if (j + kAhead < kItems) rk_load(j + kAhead);
-      const int c = j / kOutIters, it = j % kOutIters;
-      const int idx = rl + kRoleLanes * it;
-      if (idx < nv) {
-        const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
-        const T r = ra * rv[j] + dt * so[c * 16 * Np + idx];
-        res[g] = r;
-        uo[g] = uv[j] + rb * r;
+    for (int c = 0; c < 3; ++c) {
+      T ov[kOutIters];
+#pragma unroll
+      for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
+#pragma unroll
+      for (int it = 0; it < kOutIters; ++it) {
+        const int j = c * kOutIters + it;
+        if (j + kAhead < kItems) rk_load(j + kAhead);
+        const int idx = rl + kRoleLanes * it;
+        if (idx < nv) {
+          const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
+          const T r = ra * rv[j] + dt * ov[it];
+          res[g] = r;
+          uo[g] = uv[j] + rb * r;
+        }
       }
     }
   }
