@@ -352,6 +352,41 @@ def test_batch_modes_agree_bitwise_and_match_oracle(dg, precision):
     assert err < (1e-10 if precision == "fp64" else 1e-5)
 
 
+def test_fp64_batch_past_the_cache_size(dg):
+    """FP64 batch whose step touches more than the 256 MB last-level cache
+    (K = 82,944 at N = 4: 3 x 139 MB), so its stages write through streaming
+    stores: the three modes agree bitwise, and the small problem of the batch
+    matches the oracle after two steps."""
+    import torch
+    _say("[gpu] fp64 batch past the cache size")
+    specs = [(4, 24, 0), (3, 2, 21)]
+    meshes, oms, us = [], [], []
+    for N, k, seed in specs:
+        VX, EToV = I.kuhn_cube(k, 0.1, seed)
+        meshes.append((N, VX, EToV))
+        m = Me.Mesh(N, VX, EToV)
+        oms.append(m)
+        us.append(I.cavity_mode(m.x, m.y, m.z) + I.field_noise((6, m.K, m.Np), 1e-3, seed + 1))
+    dts = [D.dt_cfl(m, 0.5) for m in oms]
+    results = {}
+    for mode in ("graph", "grouped", "per_problem"):
+        b = dg.Batch(meshes, "fp64")
+        du = [p.pack(u) for p, u in zip(b.problems, us)]
+        res = [p.zeros_state() for p in b.problems]
+        b.rk_step(du, res, dts, 2, mode)
+        torch.cuda.synchronize()
+        results[mode] = [p.unpack(x) for p, x in zip(b.problems, du)]
+        b.close()
+        del du, res
+    for i in range(len(specs)):
+        assert np.array_equal(results["graph"][i], results["per_problem"][i])
+        assert np.array_equal(results["grouped"][i], results["per_problem"][i])
+    ref = L.integrate(lambda v, t: Mx.rhs(oms[1], v), us[1], 0.0, dts[1], 2)
+    err = _rel(results["graph"][1], ref)
+    _say(f"  small problem vs oracle after 2 steps: {err:.3e}")
+    assert err < 1e-12
+
+
 def test_batch_rejects_mixed_precision_and_unsupported(dg):
     VX, EToV = I.kuhn_cube(1, 0.0, 0)
     descs = (dg.MeshDesc * 2)()
