@@ -94,7 +94,9 @@ typedef struct {
  * c * field_stride; inside a field, element k's Np nodal values are
  * contiguous at offset k * Np.  Entries between K*Np and field_stride are
  * padding: never read as data.  state_elems = 6 * field_stride scalars of
- * elem_bytes bytes each. */
+ * elem_bytes bytes each.  State arrays passed to the library must start on a
+ * 16-byte boundary (hipMalloc gives 256); the kernels write them with 16-byte
+ * stores. */
 typedef struct {
   int32_t N, Np, Nfp, precision;
   int64_t K;
@@ -125,7 +127,8 @@ dg_status dg_info_get(dg_problem p, dg_info* info);
  * the header comment).  u, rhs: device pointers to state arrays in the
  * problem's precision and layout; they must not overlap.  Asynchronous on
  * stream.  Only the K*Np entries of each field of rhs are written.
- * Errors: DG_EINVAL (null pointer or u == rhs), DG_EHIP (launch failure). */
+ * Errors: DG_EINVAL (null pointer, u == rhs, or a pointer not 16-byte
+ * aligned), DG_EHIP (launch failure). */
 dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
 
 /* Kernel variants of the right-hand side, all computing the same operator:
@@ -163,7 +166,8 @@ dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, in
  * (u or the scratch) and writes the other, so a call whose 5 * nsteps stages
  * are odd in number ends with one device copy of the state back into u:
  * step many times per call rather than once per call.
- * Errors: DG_EINVAL (null pointer, u == res, nsteps < 0, dt not finite). */
+ * Errors: DG_EINVAL (null pointer, u == res, a pointer not 16-byte aligned,
+ * nsteps < 0, dt not finite). */
 dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
                      int32_t nsteps, void* stream);
 
@@ -192,8 +196,8 @@ dg_status dg_batch_problem(dg_batch b, int32_t i, dg_problem* p);
  * directly; mode 2: one launch per problem and stage (dg_rk_step per
  * problem).  All modes give bitwise identical results.  Asynchronous on
  * stream; the descriptor upload (when pointers or dt change) is staged
- * before the call returns.  Errors: DG_EINVAL (null or aliasing pointers,
- * nsteps < 0, dt not finite, mode), DG_EHIP. */
+ * before the call returns.  Errors: DG_EINVAL (null, aliasing or not
+ * 16-byte aligned pointers, nsteps < 0, dt not finite, mode), DG_EHIP. */
 dg_status dg_rk_step_batch(dg_batch b, void* const* u, void* const* res, const double* dt,
                            int32_t nsteps, int32_t mode, void* stream);
 

@@ -396,6 +396,7 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream) {
   clear_error();
   if (!p || !u || !rhs) return fail(DG_EINVAL, "null argument");
   if (u == rhs) return fail(DG_EINVAL, "u and rhs must not alias");
+  if (!aligned16(u) || !aligned16(rhs)) return fail(DG_EINVAL, "state arrays must be 16-byte aligned");
   if (!p->ks.rhs) return fail(DG_EUNSUPPORTED, "no kernel for this order/precision");
   hipError_t e = p->ks.rhs(rhs_args(p, u, rhs), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
@@ -439,6 +440,7 @@ dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int3
   (void)t;
   if (!p || !u || !res) return fail(DG_EINVAL, "null argument");
   if (u == res) return fail(DG_EINVAL, "u and res must not alias");
+  if (!aligned16(u) || !aligned16(res)) return fail(DG_EINVAL, "state arrays must be 16-byte aligned");
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);

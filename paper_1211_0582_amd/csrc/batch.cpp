@@ -206,6 +206,8 @@ dg_status dg_rk_step_batch(dg_batch b, void* const* u, void* const* res, const d
   const size_t n = b->problems.size();
   for (size_t i = 0; i < n; ++i) {
     if (!u[i] || !res[i] || u[i] == res[i]) return fail(DG_EINVAL, "problem " + std::to_string(i) + ": bad u/res");
+    if (!aligned16(u[i]) || !aligned16(res[i]))
+      return fail(DG_EINVAL, "problem " + std::to_string(i) + ": state arrays must be 16-byte aligned");
     if (!std::isfinite(dt[i])) return fail(DG_EINVAL, "problem " + std::to_string(i) + ": dt not finite");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);

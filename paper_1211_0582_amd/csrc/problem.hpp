@@ -34,5 +34,8 @@ extern const double kRkB[5];
 // could not stay resident for the next launch, and such stores retire sooner.
 constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;
 
+// The kernels write state arrays with 16-byte stores.
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 // Kernel arguments of a right-hand-side evaluation of p.
 dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs);

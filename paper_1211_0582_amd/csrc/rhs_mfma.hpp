@@ -714,7 +714,12 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   const int nv = ne * Np;
   constexpr int kRoleLanes = 64 * (WPT / 2);
   const int rl = lane + 64 * rh;      // lane within the role
-  constexpr int kOutIters = (16 * Np + kRoleLanes - 1) / kRoleLanes;
+  // Output traffic in 16-byte accesses of V consecutive values per lane: a
+  // tile's run of a field is 16 Np values, 16-byte aligned (fields start on
+  // 256-byte boundaries and 16 Np sizeof(T) is a multiple of 16).
+  constexpr int V = 16 / int(sizeof(T));
+  using VT = T __attribute__((ext_vector_type(V)));
+  constexpr int kOutIters = (16 * Np + V * kRoleLanes - 1) / (V * kRoleLanes);
   // Runge-Kutta stage: the residual and state loads of the update are issued
   // before the accumulators go through LDS, up to kAhead (component, slot)
   // items at a time, so their latency overlaps the exchange and the stores of
@@ -722,16 +727,19 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // the compiler), so it goes into the vector offset: a per-lane scalar
   // offset would make every load a waterfall loop.
   constexpr int kItems = 3 * kOutIters;
-  constexpr int kAheadRegs = sizeof(T) == 8 ? 112 : 48;  // VGPRs given to loads in flight
-  constexpr int kAhead = RK ? (kItems * 2 * int(sz / 4) <= kAheadRegs ? kItems : kAheadRegs / (2 * int(sz / 4))) : 0;
-  T rv[RK ? kItems : 1], uv[RK ? kItems : 1];
+  constexpr int kAheadRegs = sizeof(T) == 8 ? 112 : 40;  // VGPRs given to loads in flight
+  constexpr int kAhead = RK ? (kItems * 8 <= kAheadRegs ? kItems : kAheadRegs / 8) : 0;
+  VT rv[RK ? kItems : 1], uv[RK ? kItems : 1];
   const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.res, RK ? 6u * uint32_t(fs) * sz : 0u);
+  auto vload = [&](__amdgpu_buffer_rsrc_t r, uint32_t vo) {
+    return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, 0, 0));
+  };
   auto rk_load = [&](int j) {
     const int c = j / kOutIters, it = j % kOutIters;
-    const int idx = rl + kRoleLanes * it;
+    const int idx = V * (rl + kRoleLanes * it);
     const uint32_t vo = idx < nv ? uint32_t((3 * h + c) * fs + k0 * Np + idx) * sz : kOob;
-    rv[j] = buf_load<T>(rr, vo, 0);
-    uv[j] = buf_load<T>(ru, vo, 0);
+    rv[j] = vload(rr, vo);
+    uv[j] = vload(ru, vo);
   };
 #pragma unroll
   for (int j = 0; j < kAhead; ++j) rk_load(j);
@@ -747,12 +755,60 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
       }
   __syncthreads();
-  // Staged value (component c, slot it) of this lane, read without a branch
+  // Staged values (component c, slot it) of this lane, read without a branch
   // (the index is clamped into the component's rows) so that a component's
   // reads are issued together rather than one per store.
   auto so_at = [&](int c, int it) {
-    const int idx = rl + kRoleLanes * it;
-    return so[c * 16 * Np + (idx < 16 * Np ? idx : 16 * Np - 1)];
+    const int idx = V * (rl + kRoleLanes * it);
+    return *reinterpret_cast<const VT*>(&so[c * 16 * Np + (idx < 16 * Np ? idx : 16 * Np - V)]);
+  };
+  // Store of V values at p[idx..]: one 16-byte store, or per value at the
+  // end of a ragged tile.
+  auto put = [&](auto streaming, T* p, int idx, VT v) {
+    if (idx + V <= nv) {
+      if constexpr (decltype(streaming)::value)
+        __builtin_nontemporal_store(v, reinterpret_cast<VT*>(p + idx));
+      else
+        *reinterpret_cast<VT*>(p + idx) = v;
+    } else {
+#pragma unroll
+      for (int w = 0; w < V; ++w)
+        if (idx + w < nv) p[idx + w] = v[w];
+    }
+  };
+  auto out = [&](auto streaming) {
+    if constexpr (!RK) {
+      T* __restrict__ rhs = static_cast<T*>(a.rhs);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        VT ov[kOutIters];
+#pragma unroll
+        for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
+        T* base = rhs + (3 * h + c) * fs + k0 * Np;
+#pragma unroll
+        for (int it = 0; it < kOutIters; ++it) put(streaming, base, V * (rl + kRoleLanes * it), ov[it]);
+      }
+    } else {
+      T* __restrict__ res = static_cast<T*>(a.res);
+      T* __restrict__ uo = static_cast<T*>(a.u_out);
+      const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        VT ov[kOutIters];
+#pragma unroll
+        for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
+        const int64_t g = (3 * h + c) * fs + k0 * Np;
+#pragma unroll
+        for (int it = 0; it < kOutIters; ++it) {
+          const int j = c * kOutIters + it;
+          if (j + kAhead < kItems) rk_load(j + kAhead);
+          const VT r = ra * rv[j] + dt * ov[it];
+          const int idx = V * (rl + kRoleLanes * it);
+          put(streaming, res + g, idx, r);
+          put(streaming, uo + g, idx, uv[j] + rb * r);
+        }
+      }
+    }
   };
   // FP64 outputs go through streaming (non-temporal) stores when the host
   // says the arrays a launch touches exceed the last-level cache: there they
@@ -762,81 +818,11 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // kernel carries both store forms, so they keep plain stores only.
   if constexpr (sizeof(T) == 8) {
     if (a.stream_out) {
-      if constexpr (!RK) {
-        T* __restrict__ rhs = static_cast<T*>(a.rhs);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T ov[kOutIters];
-#pragma unroll
-          for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
-#pragma unroll
-          for (int it = 0; it < kOutIters; ++it) {
-            const int idx = rl + kRoleLanes * it;
-            if (idx < nv) __builtin_nontemporal_store(ov[it], &rhs[(3 * h + c) * fs + k0 * Np + idx]);
-          }
-        }
-      } else {
-        T* __restrict__ res = static_cast<T*>(a.res);
-        T* __restrict__ uo = static_cast<T*>(a.u_out);
-        const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T ov[kOutIters];
-#pragma unroll
-          for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
-#pragma unroll
-          for (int it = 0; it < kOutIters; ++it) {
-            const int j = c * kOutIters + it;
-            if (j + kAhead < kItems) rk_load(j + kAhead);
-            const int idx = rl + kRoleLanes * it;
-            if (idx < nv) {
-              const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
-              const T r = ra * rv[j] + dt * ov[it];
-              __builtin_nontemporal_store(r, &res[g]);
-              __builtin_nontemporal_store(uv[j] + rb * r, &uo[g]);
-            }
-          }
-        }
-      }
+      out(std::true_type{});
       return;
     }
   }
-  if constexpr (!RK) {
-    T* __restrict__ rhs = static_cast<T*>(a.rhs);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T ov[kOutIters];
-#pragma unroll
-      for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
-#pragma unroll
-      for (int it = 0; it < kOutIters; ++it) {
-        const int idx = rl + kRoleLanes * it;
-        if (idx < nv) rhs[(3 * h + c) * fs + k0 * Np + idx] = ov[it];
-      }
-    }
-  } else {
-    T* __restrict__ res = static_cast<T*>(a.res);
-    T* __restrict__ uo = static_cast<T*>(a.u_out);
-    const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T ov[kOutIters];
-#pragma unroll
-      for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
-#pragma unroll
-      for (int it = 0; it < kOutIters; ++it) {
-        const int j = c * kOutIters + it;
-        if (j + kAhead < kItems) rk_load(j + kAhead);
-        const int idx = rl + kRoleLanes * it;
-        if (idx < nv) {
-          const int64_t g = (3 * h + c) * fs + k0 * Np + idx;
-          const T r = ra * rv[j] + dt * ov[it];
-          res[g] = r;
-          uo[g] = uv[j] + rb * r;
-        }
-      }
-    }
-  }
+  out(std::false_type{});
 }
 
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous range of the

@@ -226,6 +226,25 @@ def test_rhs_rejects_aliasing(dg):
     p.close()
 
 
+def test_state_arrays_must_be_16_byte_aligned(dg):
+    """The kernels write state arrays with 16-byte stores: a state array that
+    starts 8 bytes into an allocation is refused before any launch."""
+    import torch
+    VX, EToV = I.kuhn_cube(1, 0.0, 0)
+    p = dg.Problem(2, VX, EToV, "fp64")
+    n = p.info.state_elems
+    buf = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    good, off = buf[:n], buf[1:]
+    res = p.zeros_state()
+    for call in (lambda: p.rhs(off, res), lambda: p.rhs(good, off), lambda: p.rk_step(off, res, 0.0, 1e-3, 1)):
+        with pytest.raises(dg.DgError) as e:
+            call()
+        assert e.value.status == dg.DG_EINVAL and "16-byte" in str(e.value)
+    p.rhs(good, res)
+    torch.cuda.synchronize()
+    p.close()
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_config2_full_size(dg, precision, variant):
