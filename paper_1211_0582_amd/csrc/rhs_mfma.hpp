@@ -9,22 +9,25 @@
 // at the 4 Nfp face nodes.  A workgroup of two waves owns a tile of 16
 // elements: wave 0 produces the E equations, wave 1 the H equations, each as
 // MFMAs with rows = nodes i (Np padded to 16), columns = the 16 elements,
-// depth = [Dr | Ds | Dt | LIFT] columns (each padded to 4).
+// depth = [Dr | Ds | Dt | LIFT] columns (each padded to 4).  At high order
+// (enough 16-row blocks) each role is split over two waves by row blocks,
+// four waves per tile.
 //
 //  * The operator is pre-swizzled on the host into MFMA A-fragments
 //    (row block ib, depth step kg, lane) and streamed through L1/L2 (one
 //    coalesced load feeds three MFMAs, one per output component).
 //  * The tile's fields sit in LDS as [c][j][e] (16 elements fastest), read in
 //    B-fragment layout; X_d is formed in registers.
-//  * The flux is evaluated once per (element, face node) by all 128 lanes:
+//  * The flux is evaluated once per (element, face node) by all lanes:
 //    the neighbour trace comes through the orientation table (a wall reads
 //    the own node and mirrors it), and the fluxes are staged in LDS in
 //    B-fragment order over the field tile for the LIFT MFMAs -- the facial
 //    buffer of the paper's split pipeline never reaches HBM.
-//  * Epilogue: accumulators go through LDS to coalesced stores; in the
-//    Runge-Kutta mode the stage update res <- a res + dt rhs,
+//  * Epilogue: accumulators go through LDS to coalesced 16-byte stores; in
+//    the Runge-Kutta mode the stage update res <- a res + dt rhs,
 //    u_out <- u + b res is applied there (u_out is a second state buffer, as
-//    neighbours still read u during the stage).
+//    neighbours still read u during the stage).  FP64 launches past the
+//    last-level cache store through streaming stores.
 //  * Tiles are mapped to workgroups so that each of the 8 XCDs gets a
 //    contiguous range of elements (neighbours then share that XCD's L2).
 #pragma once

@@ -17,19 +17,26 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def source_hash() -> str:
-    """sha256 over the HIP/C++ sources of the library (sorted by name)."""
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
+def source_hash(csrc: str | None = None) -> str:
+    """sha256 over the HIP/C++ sources of the library (sorted by name), with
+    comments and whitespace removed: only a change of the code itself makes a
+    recorded traffic figure stale."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    for path in sorted(glob.glob(os.path.join(csrc or os.path.join(HERE, "csrc"), "*"))):
         if path.endswith((".hip", ".hpp", ".cpp")):
             h.update(os.path.basename(path).encode())
-            with open(path, "rb") as f:
-                h.update(f.read())
+            with open(path, encoding="utf-8") as f:
+                code = _COMMENT.sub(" ", f.read())
+            h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 
