@@ -154,13 +154,15 @@ dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
 
   // MFMA A-fragments: row block ib, depth step kg, lane l holds
   // Op[16 ib + l % 16][depth column of (kg, l / 16)] with Op = [Dr|Ds|Dt|LIFT],
-  // each direction's depth padded from Np to a multiple of 4 with zeros.
+  // each direction's depth padded from Np to a multiple of 4 with zeros.  An
+  // extra block RB repeats the last block in the 4-row MFMA layout, lane l
+  // holding Op[16 (RB - 1) + l % 4][depth column of (kg, l / 16)].
   const int Np4 = (Np + 3) & ~3, RB = (Np + 15) / 16, KSV = Np4 / 4, KSL = NF / 4, KS = 3 * KSV + KSL;
-  std::vector<T> frag(size_t(RB) * KS * 64, T(0));
-  for (int ib = 0; ib < RB; ++ib)
+  std::vector<T> frag(size_t(RB + 1) * KS * 64, T(0));
+  for (int ib = 0; ib <= RB; ++ib)
     for (int kg = 0; kg < KS; ++kg)
       for (int l = 0; l < 64; ++l) {
-        const int row = 16 * ib + (l & 15), q = l >> 4;
+        const int row = ib < RB ? 16 * ib + (l & 15) : 16 * (RB - 1) + (l & 3), q = l >> 4;
         double v = 0.0;
         if (row < Np) {
           if (kg < 3 * KSV) {

@@ -55,6 +55,15 @@ struct Mfma16<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static constexpr int row(int q, int r) { return 4 * q + r; }
+  // 4-row form (16 blocks of 4x4, depth 1 each): block l / 4 takes A row i
+  // from lane 4 (l / 4) + i and B column j from lane 4 (l / 4) + j, which in
+  // the 16x16x4 B layout is depth l / 16 of element l % 16; lane l register
+  // r receives row r, element l % 16, summed over depth l / 16 only (the four
+  // lane groups are added at the end).  Measured on gfx950 with one-hot
+  // operands; same flop rate as the 16x16x4 form.
+  __device__ static inline acc mac4(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+  }
 };
 template <>
 struct Mfma16<double> {
@@ -63,6 +72,15 @@ struct Mfma16<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   __device__ static constexpr int row(int q, int r) { return q + 4 * r; }
+  // 4-row form (4 blocks of 4x4x4): block b = (l % 16) / 4 takes A[i][k] from
+  // lane 16 k + 4 b + i and B[k][j] from lane 16 k + 4 b + j -- the 16x16x4 B
+  // layout again -- and lane l receives row l / 16 of element l % 16 in one
+  // scalar, kept in component 0.  Measured on gfx950 with one-hot operands;
+  // same flop rate as the 16x16x4 form.
+  __device__ static inline acc mac4(double a, double b, acc c) {
+    c[0] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c[0], 0, 0, 0);
+    return c;
+  }
 };
 
 template <int N>
@@ -110,6 +128,15 @@ constexpr int waves_per_tile() {
   // MI355X four waves win from N = 5 for FP64/FP32 and from N = 6 for them.
   constexpr int min_rb = MIX == 0 ? 4 : 6;
   return (RB >= min_rb && RB % 2 == 0) ? 4 : 2;
+}
+
+// Whether the last 16-row block, which holds at most 4 nodes (N = 1, 3, 4),
+// runs on the 4-row MFMA form: a quarter of a full block's matrix-core time.
+// Two-wave tiles only (the block then belongs to both role waves).
+template <int N, typename T, int MIX>
+constexpr bool mfma_tail() {
+  using S = MfmaShape<N>;
+  return MIX == 0 && waves_per_tile<N, T, MIX>() == 2 && S::Np - 16 * (S::RB - 1) <= 4;
 }
 
 template <int N, typename T>
@@ -192,7 +219,16 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
   constexpr int KS = S::KS, TS = S::TS, TQ = S::TQ;
   constexpr uint32_t sz = sizeof(T);
   const int e = lane & 15, q = lane >> 4;
-  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag, uint32_t(S::RB * KS * 64) * sz);
+  // The fragment array holds the RB row blocks, then the last block again in
+  // the 4-row layout (lane l: row 16 (RB - 1) + l % 4, depth l / 16).
+  constexpr bool TAIL = mfma_tail<N, T, 0>() && RBW == S::RB;
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag, uint32_t((S::RB + 1) * KS * 64) * sz);
+  auto mac = [&](int ib, T av, T bv, acc_t c) -> acc_t {
+    if constexpr (TAIL) {
+      if (ib == RB - 1) return M::mac4(av, bv, c);
+    }
+    return M::mac(av, bv, c);
+  };
 
 #pragma unroll
   for (int ib = 0; ib < RB; ++ib)
@@ -208,7 +244,8 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
   const uint32_t lane_off = uint32_t(lane + rb0 * KS * 64) * sz;
   auto frag_of = [&](int step, int ib) -> T {
     const int kg = step < NV ? (step % 3) * KSV + step / 3 : 3 * KSV + (step - NV);
-    return buf_load<T>(rf, lane_off, uint32_t((ib * KS + kg) * 64) * sz);
+    const int blk = (TAIL && ib == RB - 1) ? S::RB : ib;
+    return buf_load<T>(rf, lane_off, uint32_t((blk * KS + kg) * 64) * sz);
   };
   T Abuf[kPre + 1][RB];
 #pragma unroll
@@ -243,7 +280,7 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
 #pragma unroll
       for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[ib][c] = M::mac(Abuf[step % (kPre + 1)][ib], X[c], acc[ib][c]);
+        for (int c = 0; c < 3; ++c) acc[ib][c] = mac(ib, Abuf[step % (kPre + 1)][ib], X[c], acc[ib][c]);
       if constexpr (IL) {
 #pragma unroll
         for (int fi = 0; fi < NFI; ++fi)
@@ -281,7 +318,7 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
 #pragma unroll
       for (int ib = 0; ib < RB; ++ib)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[ib][c] = M::mac(Abuf[step % (kPre + 1)][ib], F[c], acc[ib][c]);
+        for (int c = 0; c < 3; ++c) acc[ib][c] = mac(ib, Abuf[step % (kPre + 1)][ib], F[c], acc[ib][c]);
     }
   };
   if constexpr (!HALF) {
@@ -296,6 +333,18 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
     flux_store(1);
     __syncthreads();
     lift(S::HB / 4, KSL, S::HB);
+  }
+  // FP32 4-row block: add the partial sums of the four depth lane groups.
+  if constexpr (TAIL && sizeof(T) == 4) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T v = acc[RB - 1][c][r];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        acc[RB - 1][c][r] = v;
+      }
   }
 }
 
@@ -748,15 +797,32 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   for (int j = 0; j < kAhead; ++j) rk_load(j);
   __syncthreads();
   T* so = t.su + h * (3 * 16 * Np);
+  constexpr bool TAIL = mfma_tail<N, T, MIX>();
 #pragma unroll
   for (int ib = 0; ib < RBW; ++ib)
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+      if (TAIL && ib == RBW - 1) {
+        // 4-row block: FP64 row q in component 0; FP32 rows r, reduced over
+        // the lane groups, written by group 0.
+        if constexpr (sizeof(T) == 8) {
+          const int i = 16 * ib + q;
+          if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][0];
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * ib + r;
+            if (q == 0 && i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
+          }
+        }
+        continue;
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * (rb0 + ib) + M::row(q, r);
         if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
       }
+    }
   __syncthreads();
   // Staged values (component c, slot it) of this lane, read without a branch
   // (the index is clamped into the component's rows) so that a component's
