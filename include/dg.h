@@ -133,9 +133,9 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
 
 /* Kernel variants of the right-hand side, all computing the same operator:
  *   0 "valu": one workgroup per element tile on the vector ALUs;
- *   1 "mfma": one wave per 16 elements, the contraction with
- *             [Dr|Ds|Dt|LIFT] on the matrix cores, Runge-Kutta stage fused
- *             into its epilogue;
+ *   1 "mfma": one workgroup (2 or 4 waves) per tile of 16 elements, the
+ *             contraction with [Dr|Ds|Dt|LIFT] on the matrix cores,
+ *             Runge-Kutta stage fused into its epilogue;
  *   2 "mfma_p": the same contraction in persistent workgroups (one per CU)
  *             that walk a range of element tiles with the operator held in
  *             LDS and the next tile's fields loaded behind the contraction
