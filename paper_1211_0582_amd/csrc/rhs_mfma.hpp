@@ -130,13 +130,16 @@ constexpr int waves_per_tile() {
   return (RB >= min_rb && RB % 2 == 0) ? 4 : 2;
 }
 
-// Whether the last 16-row block, which holds at most 4 nodes (N = 1, 3, 4),
-// runs on the 4-row MFMA form: a quarter of a full block's matrix-core time.
-// Two-wave tiles only (the block then belongs to both role waves).
+// Whether the last 16-row block, which holds at most 4 nodes (N = 1, 3, 4,
+// 6), runs on the 4-row MFMA form: a quarter of a full block's matrix-core
+// time.  With two waves per tile the block belongs to both role waves; with
+// four, to the wave of each role that owns the upper row blocks, which then
+// runs its own copy of the wave code -- in FP32 at N = 6 that copy would cost
+// a wave per SIMD (168 -> 184 registers), so there only FP64 uses it.
 template <int N, typename T, int MIX>
 constexpr bool mfma_tail() {
   using S = MfmaShape<N>;
-  return MIX == 0 && waves_per_tile<N, T, MIX>() == 2 && S::Np - 16 * (S::RB - 1) <= 4;
+  return MIX == 0 && S::Np - 16 * (S::RB - 1) <= 4 && (waves_per_tile<N, T, MIX>() == 2 || sizeof(T) == 8);
 }
 
 template <int N, typename T>
@@ -207,8 +210,8 @@ struct FluxSchedule {
 // waits for the tile's readers and writes the fluxes over the field tile.
 // The wave produces row blocks rb0 .. rb0 + RBW - 1 of its three components
 // (all RB blocks with two waves per tile, half of them with four).
-template <int N, typename T, int H, bool IL, int NFI, int RBW, typename Tile, typename Gather, typename FluxStep,
-          typename FluxStore>
+template <int N, typename T, int H, bool IL, int NFI, int RBW, bool TW, typename Tile, typename Gather,
+          typename FluxStep, typename FluxStore>
 __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], int lane, int rb0,
                                  typename Mfma16<T>::acc (&acc)[RBW][3], Gather&& gather,
                                  FluxStep&& flux_step, FluxStore&& flux_store) {
@@ -221,7 +224,7 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
   const int e = lane & 15, q = lane >> 4;
   // The fragment array holds the RB row blocks, then the last block again in
   // the 4-row layout (lane l: row 16 (RB - 1) + l % 4, depth l / 16).
-  constexpr bool TAIL = mfma_tail<N, T, 0>() && RBW == S::RB;
+  constexpr bool TAIL = TW;  // this wave's last row block is the 4-row one
   const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag, uint32_t((S::RB + 1) * KS * 64) * sz);
   auto mac = [&](int ib, T av, T bv, acc_t c) -> acc_t {
     if constexpr (TAIL) {
@@ -244,7 +247,9 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
   const uint32_t lane_off = uint32_t(lane + rb0 * KS * 64) * sz;
   auto frag_of = [&](int step, int ib) -> T {
     const int kg = step < NV ? (step % 3) * KSV + step / 3 : 3 * KSV + (step - NV);
-    const int blk = (TAIL && ib == RB - 1) ? S::RB : ib;
+    // lane_off already points at block rb0 = S::RB - RB for a tail wave, so
+    // the 4-row block (absolute index S::RB) is block RB from there.
+    const int blk = (TAIL && ib == RB - 1) ? RB : ib;
     return buf_load<T>(rf, lane_off, uint32_t((blk * KS + kg) * 64) * sz);
   };
   T Abuf[kPre + 1][RB];
@@ -747,10 +752,24 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   static_assert(WPT == 2 || (!IL && !LIFT_HALF), "interleaved flux and split lift assume 128 lanes per tile");
   acc_t acc[RBW][3];
   if constexpr (MIX == 0) {
-    if (h == 0)
-      mfma_wave<N, T, 0, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
-    else
-      mfma_wave<N, T, 1, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
+    constexpr bool TAIL = mfma_tail<N, T, MIX>();
+    auto role = [&](auto tw) {
+      constexpr bool TW = decltype(tw)::value;
+      if (h == 0)
+        mfma_wave<N, T, 0, IL, kFluxIters, RBW, TW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
+      else
+        mfma_wave<N, T, 1, IL, kFluxIters, RBW, TW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
+    };
+    if constexpr (!TAIL) {
+      role(std::false_type{});
+    } else if constexpr (WPT == 2) {
+      role(std::true_type{});
+    } else {
+      if (rh == 1)
+        role(std::true_type{});
+      else
+        role(std::false_type{});
+    }
   } else {
     using H16 = typename std::conditional<(MIX <= 3), __bf16, _Float16>::type;
     constexpr int NPROD = MIX <= 3 ? MIX : MIX - 3;
@@ -798,20 +817,21 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   __syncthreads();
   T* so = t.su + h * (3 * 16 * Np);
   constexpr bool TAIL = mfma_tail<N, T, MIX>();
+  const bool tail_wave = TAIL && rb0 + RBW == RB;
 #pragma unroll
   for (int ib = 0; ib < RBW; ++ib)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      if (TAIL && ib == RBW - 1) {
+      if (ib == RBW - 1 && tail_wave) {
         // 4-row block: FP64 row q in component 0; FP32 rows r, reduced over
         // the lane groups, written by group 0.
         if constexpr (sizeof(T) == 8) {
-          const int i = 16 * ib + q;
+          const int i = 16 * (rb0 + ib) + q;
           if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][0];
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = 16 * ib + r;
+            const int i = 16 * (rb0 + ib) + r;
             if (q == 0 && i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
           }
         }
