@@ -25,7 +25,14 @@ __all__ = [
     "field_noise",
     "batch_draws",
     "k_for_dofs",
+    "FACE_VERTS",
+    "cube_face_bc",
+    "random_face_bc",
 ]
+
+#: local vertices of face f of a tetrahedron, in the face numbering of the
+#: library's interface (face_bc[k][f] refers to face f of element k)
+FACE_VERTS = ((0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3))
 
 # The six axis permutations; tetrahedron p of a cube walks the cube corners
 # v0 -> v0+e[p0] -> v0+e[p0]+e[p1] -> v0+(1,1,1).
@@ -125,3 +132,28 @@ def k_for_dofs(N: int, dofs_per_field: float = 1e7) -> int:
     nodal values per field at order N."""
     Np = (N + 1) * (N + 2) * (N + 3) // 6
     return int(round((dofs_per_field / (6 * Np)) ** (1.0 / 3.0)))
+
+
+def cube_face_bc(VX, EToV, sides):
+    """Boundary-condition codes per (element, face) for a mesh of the unit cube.
+
+    ``sides`` maps a cube side name ("x0", "x1", "y0", "y1", "z0", "z1": the
+    plane x = 0, x = 1, ...) to a code; a face whose three vertices lie on that
+    plane gets it, every other face 0.  Returns (K, 4) int8.
+    """
+    VX = np.asarray(VX, dtype=np.float64)
+    EToV = np.asarray(EToV)
+    out = np.zeros((EToV.shape[0], 4), dtype=np.int8)
+    for f, fv in enumerate(FACE_VERTS):
+        pts = VX[EToV[:, list(fv)]]                       # (K, 3, 3)
+        for name, code in sides.items():
+            axis, val = "xyz".index(name[0]), float(name[1])
+            on = np.all(np.abs(pts[:, :, axis] - val) < 1e-12, axis=1)
+            out[on, f] = code
+    return out
+
+
+def random_face_bc(K: int, seed: int, codes=(0, 1, 2)):
+    """Seeded uniform draw of a code per (element, face): (K, 4) int8."""
+    rng = np.random.default_rng(seed)
+    return np.asarray(codes, dtype=np.int8)[rng.integers(0, len(codes), size=(K, 4))]

@@ -7,10 +7,14 @@ global-matrix definitions (Section 2) with M^k = J_k M (Section 2.1).
 Dissipation: for the scheme and flux of ``oracle.maxwell`` the discrete
 energy rate is exactly
     sum_k J_k u^T M rhs_k = - alpha/2 sum_{interior faces} [ |n x dE|^2 + |n x dH|^2 ]_f
-                            - alpha   sum_{wall faces}     [ |n x E-|^2 ]_f,
-where [g]_f = sJ_f sum_c g_c^T M_f g_c integrates over the face with the face
-mass matrix (derived from the divergence of E x H, the central part of the
-flux cancelling between the two sides of every interior face).
+                            + sum_{boundary faces} ( - (a_E + a_H)/2 [ H- . (n x E-) ]_f
+                                 - alpha/2 [ (1 - a_E) |n x E-|^2 + (1 - a_H) |n x H-|^2 ]_f ),
+where [g]_f = sJ_f sum g^T M_f g integrates over the face with the face mass
+matrix and (a_E, a_H) are the boundary face's exterior-state factors
+(E+ = a_E E-, H+ = a_H H-).  It follows from the divergence of E x H (the
+volume term integrates to -[n . (E- x H-)]_f per face), the central part of
+the flux cancelling between the two sides of every interior face.  Perfectly
+conducting walls give - alpha [ |n x E-|^2 ]_f.
 ``dissipation`` evaluates the right side from traces only.
 
 Parity: ``energy``/``dissipation`` are pinned against each other through the
@@ -21,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .maxwell import rhs, traces
+from .maxwell import MIRROR, rhs, traces
 
 
 def energy(mesh, u):
@@ -43,19 +47,25 @@ def dissipation(mesh, u, alpha: float = 1.0):
     n = np.stack([mesh.nx, mesh.ny, mesh.nz])[:, :, :, None]
     Mf = mesh.re.Mf                                      # (4, Nfp, Nfp)
 
-    def face_form(g):
-        # g: (3, K, 4, Nfp) -> (K, 4) sum_c g_c^T M_f g_c
-        Mg = np.einsum("fij,ckfj->ckfi", Mf, g)
-        return np.sum(g * Mg, axis=(0, 3))
+    def face_form(g, h):
+        # g, h: (3, K, 4, Nfp) -> (K, 4) sum_c g_c^T M_f h_c
+        Mh = np.einsum("fij,ckfj->ckfi", Mf, h)
+        return np.sum(g * Mh, axis=(0, 3))
 
     ncdE = np.cross(n, uM[0:3] - uP[0:3], axis=0)
     ncdH = np.cross(n, uM[3:6] - uP[3:6], axis=0)
     ncE = np.cross(n, uM[0:3], axis=0)
+    ncH = np.cross(n, uM[3:6], axis=0)
     interior = ~bnd
-    fi = face_form(ncdE) + face_form(ncdH)
-    fb = face_form(ncE)
+    fi = face_form(ncdE, ncdE) + face_form(ncdH, ncdH)
     total = -0.5 * alpha * np.sum((mesh.sJ * fi)[interior]) * 0.5  # each interior face seen twice
-    total += -alpha * np.sum((mesh.sJ * fb)[bnd])
+    for code, (aE, aH) in MIRROR.items():
+        sel = mesh.bc == code
+        if not np.any(sel):
+            continue
+        fb = (-0.5 * (aE + aH) * face_form(uM[3:6], ncE)
+              - 0.5 * alpha * ((1.0 - aE) * face_form(ncE, ncE) + (1.0 - aH) * face_form(ncH, ncH)))
+        total += np.sum((mesh.sJ * fb)[sel])
     return float(total)
 
 

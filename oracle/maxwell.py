@@ -11,9 +11,17 @@ Flux (results section, Maxwell upwind flux; H part by E -> H, H -> -E
 duality), with jumps dE = E- - E+, dH = H- - H+:
     fE = 1/2 [ -n x dH + alpha (n (n . dE) - dE) ]
     fH = 1/2 [  n x dE + alpha (n (n . dH) - dH) ]
-and rhs += LIFT (Fscale * f).  Perfectly conducting walls use the mirror
-state E+ = -E-, H+ = H-, i.e. dE = 2 E-, dH = 0.  alpha = 1 is upwind,
-alpha = 0 central.
+and rhs += LIFT (Fscale * f).  alpha = 1 is upwind, alpha = 0 central.
+
+Boundary faces take an exterior state built from the interior trace,
+E+ = a_E E-, H+ = a_H H-, so dE = (1 - a_E) E-, dH = (1 - a_H) H-, with
+(a_E, a_H) per condition code of the mesh:
+    0  perfectly conducting wall (n x E = 0):          (-1,  1)
+    1  perfectly magnetic-conducting wall (n x H = 0): ( 1, -1)
+    2  absorbing face (no incoming wave):              ( 0,  0)
+Code 1 is code 0 seen through the E -> H, H -> -E duality of the equations;
+code 2 makes the upwind flux that of a zero exterior, so an outgoing wave
+leaves without reflection.
 
 The sign reading (the printed flux is the term subtracted, i.e. the
 n.F - (n.F)* of the scheme equals the expression above) is the one under which
@@ -58,14 +66,23 @@ def traces(mesh, u):
     return uM, uP, bnd
 
 
+#: exterior-state factors (a_E, a_H) per boundary condition code
+MIRROR = {0: (-1.0, 1.0), 1: (1.0, -1.0), 2: (0.0, 0.0)}
+
+
 def surface_flux(mesh, u, alpha: float = 1.0):
     """Fscale * [n.F - (n.F)*] at every face node: (6, K, 4, Nfp)."""
     uM, uP, bnd = traces(mesh, u)
     dE = uM[0:3] - uP[0:3]
     dH = uM[3:6] - uP[3:6]
+    aE = np.zeros(bnd.shape)
+    aH = np.zeros(bnd.shape)
+    for code, (ae, ah) in MIRROR.items():
+        aE[mesh.bc == code] = ae
+        aH[mesh.bc == code] = ah
     b = bnd[None, :, :, None]
-    dE = np.where(b, 2.0 * uM[0:3], dE)
-    dH = np.where(b, 0.0, dH)
+    dE = np.where(b, (1.0 - aE[None, :, :, None]) * uM[0:3], dE)
+    dH = np.where(b, (1.0 - aH[None, :, :, None]) * uM[3:6], dH)
     n = np.stack([mesh.nx, mesh.ny, mesh.nz])[:, :, :, None]  # (3, K, 4, 1)
     ndE = np.sum(n * dE, axis=0)
     ndH = np.sum(n * dH, axis=0)

@@ -13,7 +13,11 @@ Fscale = sJ / J.
 Connectivity (the "flux gather" of Section 2.1 picks facial nodes of the
 neighbour): faces are matched by their sorted vertex triple, face nodes by
 physical coordinates (nearest node; tolerance 1e-10 of the smallest edge).
-Unmatched faces are perfectly conducting walls.
+Unmatched faces are boundary faces.  Each boundary face carries a condition
+code (the boundary data of Section 2 on the domain boundary; the paper leaves
+the condition open): 0 perfectly conducting wall (the default), 1 perfectly
+magnetic-conducting wall, 2 absorbing face (zero exterior state).  The codes
+are read from ``face_bc[k, f]`` for unmatched faces and ignored elsewhere.
 
 Parity: pinned by tests/test_oracle_mesh.py (cube volume, boundary area,
 J = h^3/8 on the unjittered mesh, outward normals, coordinate equality of
@@ -35,9 +39,11 @@ class Mesh:
     EToE, EToF     (K, 4) neighbour element / face, -1 on the boundary
     vmapP          (K, 4, Nfp) flat index k*Np + i of the neighbour trace node,
                    -1 on boundary faces
+    bc             (K, 4) boundary condition code of boundary faces (0, 1, 2),
+                   -1 on interior faces
     """
 
-    def __init__(self, N: int, VX, EToV):
+    def __init__(self, N: int, VX, EToV, face_bc=None):
         re = ref_element(N)
         self.re = re
         self.N, self.Np, self.Nfp = N, re.Np, re.Nfp
@@ -74,6 +80,13 @@ class Mesh:
         self.sJ = area / 2.0
         self.Fscale = self.sJ / self.J[:, None]
         self._connect(X, v)
+        codes = np.zeros((K, 4), dtype=np.int64) if face_bc is None else np.asarray(face_bc, dtype=np.int64)
+        if codes.shape != (K, 4):
+            raise ValueError("face_bc must have shape (K, 4)")
+        bnd = self.EToE < 0
+        if np.any((codes[bnd] < 0) | (codes[bnd] > 2)):
+            raise ValueError("boundary condition codes must be 0, 1 or 2")
+        self.bc = np.where(bnd, codes, -1)
 
     def _connect(self, X, v):
         K, Np, Nfp = self.K, self.Np, self.Nfp

@@ -129,3 +129,78 @@ def test_least_damped_eigenvalues_are_cavity_frequencies(tiny_operator):
     up = np.sort(up.imag)
     assert np.allclose(up[:3], np.pi * np.sqrt(2.0), atol=2e-3)       # (1,1,0) triplet
     assert np.allclose(up[3:5], np.pi * np.sqrt(3.0), atol=3e-3)      # (1,1,1) pair
+
+
+# ---------------------------------------------------------------------------
+# Boundary conditions other than the perfectly conducting wall.
+# ---------------------------------------------------------------------------
+def _dual(u):
+    """E -> H, H -> -E: a symmetry of the Maxwell equations."""
+    return np.concatenate([u[3:6], -u[0:3]])
+
+
+@pytest.mark.parametrize("N,alpha", [(3, 1.0), (2, 0.5), (4, 0.0)])
+def test_magnetic_wall_is_the_dual_of_the_conducting_wall(N, alpha):
+    """A perfectly magnetic-conducting wall is a conducting wall seen through
+    the duality of the equations: rhs_PMC(dual u) = dual rhs_PEC(u)."""
+    VX, EToV = I.kuhn_cube(2, 0.1, 5)
+    pec = Me.Mesh(N, VX, EToV)
+    pmc = Me.Mesh(N, VX, EToV, np.ones((EToV.shape[0], 4), dtype=np.int8))
+    u = _fields(pec)
+    lhs = Mx.rhs(pmc, _dual(u), alpha)
+    rhs = _dual(Mx.rhs(pec, u, alpha))
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+    # and the two walls really differ
+    assert np.abs(Mx.rhs(pmc, u, alpha) - Mx.rhs(pec, u, alpha)).max() > 1e-3 * np.abs(rhs).max()
+
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_outgoing_plane_wave_with_mixed_walls_is_exact(N):
+    """E = (0, x^2, 0), H = (0, 0, x^2) is a wave moving in +x with
+    dE/dt = (0, -2x, 0), dH/dt = (0, 0, -2x).  With an absorbing face at
+    x = 1 (the wave leaves there), conducting walls at y = 0, 1 (E normal to
+    them), magnetic walls at z = 0, 1 (H normal to them) and the fields zero
+    at x = 0, every jump and every boundary penalty vanishes, so the upwind
+    scheme reproduces the exact time derivative at every node."""
+    VX, EToV = I.kuhn_cube(2, 0.1, 3)
+    bc = I.cube_face_bc(VX, EToV, {"x1": 2, "y0": 0, "y1": 0, "z0": 1, "z1": 1})
+    m = Me.Mesh(N, VX, EToV, bc)
+    u = np.zeros((6, m.K, m.Np))
+    u[1] = m.x ** 2
+    u[5] = m.x ** 2
+    ex = np.zeros_like(u)
+    ex[1] = -2 * m.x
+    ex[5] = -2 * m.x
+    assert np.abs(Mx.rhs(m, u) - ex).max() < 1e-11
+    # a conducting wall at x = 1 reflects the wave: no longer exact there
+    m0 = Me.Mesh(N, VX, EToV, I.cube_face_bc(VX, EToV, {"z0": 1, "z1": 1}))
+    assert np.abs(Mx.rhs(m0, u) - ex).max() > 0.1
+
+
+@pytest.mark.parametrize("N,alpha,seed", [(3, 1.0, 1), (2, 0.5, 2), (4, 0.0, 3), (1, 1.0, 4)])
+def test_energy_identity_with_mixed_boundary_codes(N, alpha, seed):
+    VX, EToV = I.kuhn_cube(2, 0.1, seed)
+    m = Me.Mesh(N, VX, EToV, I.random_face_bc(EToV.shape[0], seed))
+    assert set(np.unique(m.bc[m.EToE < 0])) == {0, 1, 2}
+    u = _fields(m)
+    rate = D.energy_rate(m, u, alpha)
+    diss = D.dissipation(m, u, alpha)
+    scale = D.energy(m, u) * max(1.0, np.max(m.Fscale)) * (N + 1) ** 2
+    assert abs(rate - diss) < 1e-13 * scale
+    if alpha == 0.0:
+        assert abs(rate) < 1e-13 * scale
+    else:
+        assert rate < 0.0
+
+
+def test_boundary_codes_are_checked_and_ignored_on_interior_faces():
+    VX, EToV = I.kuhn_cube(1, 0.0, 0)
+    with pytest.raises(ValueError):
+        Me.Mesh(2, VX, EToV, np.full((6, 4), 3, dtype=np.int8))
+    VX, EToV = I.kuhn_cube(2, 0.1, 0)
+    m0 = Me.Mesh(2, VX, EToV)
+    codes = np.zeros((m0.K, 4), dtype=np.int8)
+    codes[m0.EToE >= 0] = 7                      # interior entries are not read
+    m1 = Me.Mesh(2, VX, EToV, codes)
+    u = _fields(m0)
+    assert np.array_equal(Mx.rhs(m0, u), Mx.rhs(m1, u))
