@@ -1,14 +1,16 @@
 """Diagnostics for the DG oracle: energy, its exact dissipation, errors, the
 assembled operator and the time-step rule.  Test infrastructure only.
 
-Energy: E(u) = 1/2 sum_k J_k u_k^T (M (x) I_6) u_k, the M^k-norm of the
-global-matrix definitions (Section 2) with M^k = J_k M (Section 2.1).
+Energy: E(u) = 1/2 sum_k J_k (eps_k E_k^T M E_k + mu_k H_k^T M H_k), the
+M^k-norm of the global-matrix definitions (Section 2) with M^k = J_k M
+(Section 2.1), weighted by the material (1/2 sum J u^T M u for eps = mu = 1).
 
 Dissipation: for the scheme and flux of ``oracle.maxwell`` the discrete
 energy rate is exactly
-    sum_k J_k u^T M rhs_k = - alpha/2 sum_{interior faces} [ |n x dE|^2 + |n x dH|^2 ]_f
-                            + sum_{boundary faces} ( - (a_E + a_H)/2 [ H- . (n x E-) ]_f
-                                 - alpha/2 [ (1 - a_E) |n x E-|^2 + (1 - a_H) |n x H-|^2 ]_f ),
+    sum_k J_k (eps E^T M rhs_E + mu H^T M rhs_H)
+      = - alpha sum_{interior faces} [ |n x dE|^2 / (Z- + Z+) + |n x dH|^2 / (Y- + Y+) ]_f
+        + sum_{boundary faces} ( - (a_E + a_H)/2 [ H- . (n x E-) ]_f
+             - alpha/2 [ (1 - a_E) |n x E-|^2 / Z + (1 - a_H) Z |n x H-|^2 ]_f ),
 where [g]_f = sJ_f sum g^T M_f g integrates over the face with the face mass
 matrix and (a_E, a_H) are the boundary face's exterior-state factors
 (E+ = a_E E-, H+ = a_H H-).  It follows from the divergence of E x H (the
@@ -28,17 +30,23 @@ import numpy as np
 from .maxwell import MIRROR, rhs, traces
 
 
+def _material(mesh):
+    """(6, K, 1) weights eps (E fields) and mu (H fields) of the energy."""
+    return np.concatenate([np.repeat(mesh.eps[None, :], 3, axis=0),
+                           np.repeat(mesh.mu[None, :], 3, axis=0)])[:, :, None]
+
+
 def energy(mesh, u):
     u = np.asarray(u, dtype=np.float64)
     Mu = u @ mesh.re.M.T                               # (6, K, Np)
-    return 0.5 * float(np.sum(mesh.J[None, :, None] * u * Mu))
+    return 0.5 * float(np.sum(mesh.J[None, :, None] * _material(mesh) * u * Mu))
 
 
 def energy_rate(mesh, u, alpha: float = 1.0):
-    """sum_k J_k u^T M rhs_k computed through the oracle RHS."""
+    """sum_k J_k (eps E^T M rhs_E + mu H^T M rhs_H) computed through the oracle RHS."""
     r = rhs(mesh, u, alpha)
     Mr = r @ mesh.re.M.T
-    return float(np.sum(mesh.J[None, :, None] * u * Mr))
+    return float(np.sum(mesh.J[None, :, None] * _material(mesh) * u * Mr))
 
 
 def dissipation(mesh, u, alpha: float = 1.0):
@@ -57,14 +65,16 @@ def dissipation(mesh, u, alpha: float = 1.0):
     ncE = np.cross(n, uM[0:3], axis=0)
     ncH = np.cross(n, uM[3:6], axis=0)
     interior = ~bnd
-    fi = face_form(ncdE, ncdE) + face_form(ncdH, ncdH)
-    total = -0.5 * alpha * np.sum((mesh.sJ * fi)[interior]) * 0.5  # each interior face seen twice
+    Zm = np.repeat(mesh.Z[:, None], 4, axis=1)
+    Zp = np.where(bnd, Zm, mesh.Z[np.where(bnd, 0, mesh.EToE)])
+    fi = face_form(ncdE, ncdE) / (Zm + Zp) + face_form(ncdH, ncdH) / (1.0 / Zm + 1.0 / Zp)
+    total = -alpha * np.sum((mesh.sJ * fi)[interior]) * 0.5  # each interior face seen twice
     for code, (aE, aH) in MIRROR.items():
         sel = mesh.bc == code
         if not np.any(sel):
             continue
         fb = (-0.5 * (aE + aH) * face_form(uM[3:6], ncE)
-              - 0.5 * alpha * ((1.0 - aE) * face_form(ncE, ncE) + (1.0 - aH) * face_form(ncH, ncH)))
+              - 0.5 * alpha * ((1.0 - aE) * face_form(ncE, ncE) / Zm + (1.0 - aH) * Zm * face_form(ncH, ncH)))
         total += np.sum((mesh.sJ * fb)[sel])
     return float(total)
 

@@ -3,15 +3,26 @@
 The operator is the paper's semi-discrete scheme (Section 2):
     du/dt = - sum_nu D^nu F(u) + L [ n.F - (n.F)* ]   on every element,
 for the linear Maxwell flux, split as in Section 2.1 into F(u), local
-differentiation, flux gather and flux lifting.  With eps = mu = 1 and
-u = (E, H):  dE/dt = curl H, dH/dt = -curl E, so -D F(u) is the discrete curl
-built from the reference Dr, Ds, Dt and the element's constant metric.
+differentiation, flux gather and flux lifting.  With u = (E, H) and a
+permittivity eps and permeability mu constant per element (the conservation
+law of Section 2 with the material matrix on the time derivative):
+eps dE/dt = curl H, mu dH/dt = -curl E, so -D F(u) is the discrete curl built
+from the reference Dr, Ds, Dt and the element's constant metric, divided by
+eps or mu.
 
-Flux (results section, Maxwell upwind flux; H part by E -> H, H -> -E
-duality), with jumps dE = E- - E+, dH = H- - H+:
-    fE = 1/2 [ -n x dH + alpha (n (n . dE) - dE) ]
-    fH = 1/2 [  n x dE + alpha (n (n . dH) - dH) ]
-and rhs += LIFT (Fscale * f).  alpha = 1 is upwind, alpha = 0 central.
+Flux (results section, Maxwell upwind flux of the flux figure, part a; the
+H part by the E -> H, H -> -E duality), with jumps dE = E- - E+,
+dH = H- - H+, impedances Z = sqrt(mu / eps) and admittances Y = 1 / Z of the
+own (-) and neighbour (+) element:
+    fE = [ -Z+ n x dH + alpha (n (n . dE) - dE) ] / (Z- + Z+)
+    fH = [  Y+ n x dE + alpha (n (n . dH) - dH) ] / (Y- + Y+)
+and rhs += LIFT (Fscale * f) before the division by eps or mu.  With
+eps = mu = 1 this is 1/2 [ -n x dH + alpha (n (n.dE) - dE) ] and
+1/2 [ n x dE + alpha (n (n.dH) - dH) ].  alpha = 1 is upwind, alpha = 0
+central.  The weights are those of the Riemann solution between two media
+(the reading taken for the paper's generic flux); they are pinned by exact
+energy conservation of the central flux, which fails for any other
+weighting.
 
 Boundary faces take an exterior state built from the interior trace,
 E+ = a_E E-, H+ = a_H H-, so dE = (1 - a_E) E-, dH = (1 - a_H) H-, with
@@ -21,7 +32,8 @@ E+ = a_E E-, H+ = a_H H-, so dE = (1 - a_E) E-, dH = (1 - a_H) H-, with
     2  absorbing face (no incoming wave):              ( 0,  0)
 Code 1 is code 0 seen through the E -> H, H -> -E duality of the equations;
 code 2 makes the upwind flux that of a zero exterior, so an outgoing wave
-leaves without reflection.
+leaves without reflection.  A boundary face's exterior has the material of
+its element (Z+ = Z-).
 
 The sign reading (the printed flux is the term subtracted, i.e. the
 n.F - (n.F)* of the scheme equals the expression above) is the one under which
@@ -86,8 +98,12 @@ def surface_flux(mesh, u, alpha: float = 1.0):
     n = np.stack([mesh.nx, mesh.ny, mesh.nz])[:, :, :, None]  # (3, K, 4, 1)
     ndE = np.sum(n * dE, axis=0)
     ndH = np.sum(n * dH, axis=0)
-    fE = 0.5 * (-np.cross(n, dH, axis=0) + alpha * (n * ndE - dE))
-    fH = 0.5 * (np.cross(n, dE, axis=0) + alpha * (n * ndH - dH))
+    Zm = np.repeat(mesh.Z[:, None], 4, axis=1)
+    Zp = np.where(bnd, Zm, mesh.Z[np.where(bnd, 0, mesh.EToE)])
+    Zm, Zp = Zm[None, :, :, None], Zp[None, :, :, None]
+    Ym, Yp = 1.0 / Zm, 1.0 / Zp
+    fE = (-Zp * np.cross(n, dH, axis=0) + alpha * (n * ndE - dE)) / (Zm + Zp)
+    fH = (Yp * np.cross(n, dE, axis=0) + alpha * (n * ndH - dH)) / (Ym + Yp)
     f = np.concatenate([fE, fH], axis=0)
     return f * mesh.Fscale[None, :, :, None]
 
@@ -103,4 +119,6 @@ def rhs(mesh, u, alpha: float = 1.0):
     out[3], out[4], out[5] = -cx, -cy, -cz
     f = surface_flux(mesh, u, alpha).reshape(6, K, 4 * Nfp)
     out += f @ mesh.re.LIFT.T
+    out[0:3] /= mesh.eps[None, :, None]
+    out[3:6] /= mesh.mu[None, :, None]
     return out

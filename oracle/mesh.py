@@ -41,9 +41,11 @@ class Mesh:
                    -1 on boundary faces
     bc             (K, 4) boundary condition code of boundary faces (0, 1, 2),
                    -1 on interior faces
+    eps, mu        (K,) permittivity and permeability, constant per element
+                   (default 1); Z = sqrt(mu / eps) the impedance
     """
 
-    def __init__(self, N: int, VX, EToV, face_bc=None):
+    def __init__(self, N: int, VX, EToV, face_bc=None, eps=None, mu=None):
         re = ref_element(N)
         self.re = re
         self.N, self.Np, self.Nfp = N, re.Np, re.Nfp
@@ -87,6 +89,12 @@ class Mesh:
         if np.any((codes[bnd] < 0) | (codes[bnd] > 2)):
             raise ValueError("boundary condition codes must be 0, 1 or 2")
         self.bc = np.where(bnd, codes, -1)
+        self.eps = np.ones(K) if eps is None else np.asarray(eps, dtype=np.float64).reshape(K)
+        self.mu = np.ones(K) if mu is None else np.asarray(mu, dtype=np.float64).reshape(K)
+        if not (np.all(np.isfinite(self.eps)) and np.all(self.eps > 0) and np.all(np.isfinite(self.mu))
+                and np.all(self.mu > 0)):
+            raise ValueError("eps and mu must be finite and positive")
+        self.Z = np.sqrt(self.mu / self.eps)
 
     def _connect(self, X, v):
         K, Np, Nfp = self.K, self.Np, self.Nfp

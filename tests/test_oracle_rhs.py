@@ -204,3 +204,84 @@ def test_boundary_codes_are_checked_and_ignored_on_interior_faces():
     m1 = Me.Mesh(2, VX, EToV, codes)
     u = _fields(m0)
     assert np.array_equal(Mx.rhs(m0, u), Mx.rhs(m1, u))
+
+
+# ---------------------------------------------------------------------------
+# Materials: permittivity eps and permeability mu constant per element.
+# ---------------------------------------------------------------------------
+def _materials(K, seed):
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(-1.0, 1.5, K)), np.exp(rng.uniform(-1.0, 1.0, K))
+
+
+@pytest.mark.parametrize("N,alpha,seed", [(3, 1.0, 1), (2, 0.5, 2), (4, 0.0, 3), (3, 0.0, 4)])
+def test_energy_identity_with_materials(N, alpha, seed):
+    """eps- and mu-weighted energy: the rate equals the derived dissipation
+    exactly, and the central flux conserves it exactly -- which holds only
+    for the impedance weights of the flux."""
+    VX, EToV = I.kuhn_cube(2, 0.1, seed)
+    eps, mu = _materials(EToV.shape[0], seed)
+    m = Me.Mesh(N, VX, EToV, I.random_face_bc(EToV.shape[0], seed), eps, mu)
+    u = _fields(m)
+    rate = D.energy_rate(m, u, alpha)
+    diss = D.dissipation(m, u, alpha)
+    scale = D.energy(m, u) * max(1.0, np.max(m.Fscale)) * (N + 1) ** 2 * np.max(1.0 / np.minimum(eps, mu))
+    assert abs(rate - diss) < 1e-13 * scale
+    if alpha == 0.0:
+        assert abs(rate) < 1e-13 * scale
+    else:
+        assert rate < 0.0
+
+
+def test_swapped_impedance_weights_break_conservation(monkeypatch):
+    """Planted mistake on the CPU: weighting the jump by the own impedance
+    instead of the neighbour's makes the central flux gain or lose energy."""
+    VX, EToV = I.kuhn_cube(2, 0.1, 5)
+    eps, mu = _materials(EToV.shape[0], 5)
+    m = Me.Mesh(3, VX, EToV, None, eps, mu)
+    u = _fields(m)
+    good = abs(D.energy_rate(m, u, 0.0))
+    orig = Mx.surface_flux
+
+    def swapped(mesh, uu, alpha=1.0):
+        # recompute fE with Z- in place of Z+ (alpha = 0 part only)
+        uM, uP, bnd = Mx.traces(mesh, uu)
+        f = orig(mesh, uu, alpha)
+        Zm = np.repeat(mesh.Z[:, None], 4, axis=1)
+        Zp = np.where(bnd, Zm, mesh.Z[np.where(bnd, 0, mesh.EToE)])
+        f[0:3] *= (Zm / Zp)[None, :, :, None]
+        return f
+
+    monkeypatch.setattr(Mx, "surface_flux", swapped)
+    bad = abs(D.energy_rate(m, u, 0.0))
+    assert good < 1e-13 * D.energy(m, u) and bad > 1e-6 * D.energy(m, u)
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_polynomial_exactness_with_piecewise_materials(N):
+    """E = (0, 0, x(1-x)y(1-y)), H = 0 has no jumps and satisfies the
+    conducting walls, so in every element dH/dt = -curl E / mu exactly and
+    dE/dt = 0, whatever the materials."""
+    VX, EToV = I.kuhn_cube(2, 0.1, 6)
+    eps, mu = _materials(EToV.shape[0], 6)
+    m = Me.Mesh(N, VX, EToV, None, eps, mu)
+    x, y = m.x, m.y
+    u = np.zeros((6, m.K, m.Np))
+    u[2] = x * (1 - x) * y * (1 - y)
+    ex = np.zeros_like(u)
+    ex[3] = -x * (1 - x) * (1 - 2 * y) / mu[:, None]
+    ex[4] = (1 - 2 * x) * y * (1 - y) / mu[:, None]
+    assert np.abs(Mx.rhs(m, u) - ex).max() < 1e-11
+
+
+def test_homogeneous_material_scales_time():
+    """eps = mu = c everywhere: same impedance as vacuum, light speed 1/c,
+    so the right-hand side is the vacuum one divided by c."""
+    VX, EToV = I.kuhn_cube(2, 0.1, 7)
+    K = EToV.shape[0]
+    m0 = Me.Mesh(3, VX, EToV)
+    mc = Me.Mesh(3, VX, EToV, None, np.full(K, 2.5), np.full(K, 2.5))
+    u = _fields(m0)
+    assert np.abs(Mx.rhs(mc, u) - Mx.rhs(m0, u) / 2.5).max() < 1e-13 * np.abs(Mx.rhs(m0, u)).max()
+    with pytest.raises(ValueError):
+        Me.Mesh(3, VX, EToV, None, np.full(K, -1.0), None)
