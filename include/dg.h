@@ -135,11 +135,7 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
  *   0 "valu": one workgroup per element tile on the vector ALUs;
  *   1 "mfma": one workgroup (2 or 4 waves) per tile of 16 elements, the
  *             contraction with [Dr|Ds|Dt|LIFT] on the matrix cores,
- *             Runge-Kutta stage fused into its epilogue;
- *   2 "mfma_p": the same contraction in persistent workgroups (one per CU)
- *             that walk a range of element tiles with the operator held in
- *             LDS and the next tile's fields loaded behind the contraction
- *             (built where four or two tiles and the operator fit in LDS).
+ *             Runge-Kutta stage fused into its epilogue.
  * dg_setup_mesh picks "mfma" where it is built for (N, precision), else
  * "valu".  dg_variant_name returns NULL outside 0 .. dg_variant_count()-1.
  * dg_set_variant: DG_EINVAL (null p, v out of range), DG_EUNSUPPORTED (not

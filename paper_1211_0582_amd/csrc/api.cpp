@@ -237,7 +237,7 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
 }
 
 namespace {
-const char* const kVariantNames[dgd::kVariantCount] = {"valu", "mfma", "mfma_p"};
+const char* const kVariantNames[dgd::kVariantCount] = {"valu", "mfma"};
 }  // namespace
 
 extern "C" {

@@ -72,7 +72,7 @@ struct UpdateArgs {
 using RhsLauncher = hipError_t (*)(const RhsArgs&, hipStream_t);
 
 // Kernel variants of the right-hand side.
-enum Variant { kVariantValu = 0, kVariantMfma = 1, kVariantMfmaP = 2, kVariantCount = 3 };
+enum Variant { kVariantValu = 0, kVariantMfma = 1, kVariantCount = 2 };
 
 struct KernelSet {
   RhsLauncher rhs = nullptr;  // writes rhs

@@ -2,7 +2,6 @@
 // this file once per order N = 1..9 with -DDG_ORDER=N (parallel builds, small
 // objects).
 #include "rhs_mfma.hpp"
-#include "rhs_mfma_p.hpp"
 #include "rhs_valu.hpp"
 
 #ifndef DG_ORDER
@@ -30,13 +29,6 @@ KernelSet make(int variant) {
       k.tile = 16;
       k.frag_count = MfmaShape<N>::frag_count;
     }
-  } else if (variant == kVariantMfmaP) {
-    if constexpr (persist_tpw<N, T, 0>() > 0) {
-      k.rhs = &launch_rhs_mfma_p<N, T>;
-      k.rk = &launch_rk_mfma_p<N, T>;
-      k.tile = 16;
-      k.frag_count = MfmaShape<N>::frag_count;
-    }
   }
   return k;
 }
@@ -50,13 +42,6 @@ KernelSet make_mixed(int variant) {
     if constexpr (mfma_supported<N, float>()) {
       k.rhs = &launch_rhs_mfma<N, float, MIX>;
       k.rk = &launch_rk_mfma<N, float, MIX>;
-      k.tile = 16;
-      k.frag16_bytes = MixedShape<N>::frag_bytes;
-    }
-  } else if (variant == kVariantMfmaP) {
-    if constexpr (persist_tpw<N, float, MIX>() > 0) {
-      k.rhs = &launch_rhs_mfma_p<N, float, MIX>;
-      k.rk = &launch_rk_mfma_p<N, float, MIX>;
       k.tile = 16;
       k.frag16_bytes = MixedShape<N>::frag_bytes;
     }
