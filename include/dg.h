@@ -4,26 +4,36 @@
  *
  * What is computed.  The semi-discrete scheme of Kloeckner, Warburton and
  * Hesthaven, "High-Order Discontinuous Galerkin Methods by GPU
- * Metaprogramming", Section 2 ("The Discontinuous Galerkin Method", strong
- * form and the semi-discrete equation), for the linear Maxwell flux with
- * eps = mu = 1 and field order u = (Ex, Ey, Ez, Hx, Hy, Hz):
+ * Metaprogramming", Section 2 (strong form and the semi-discrete equation),
+ * for the linear Maxwell system with field order u = (Ex, Ey, Ez, Hx, Hy, Hz)
+ * and a permittivity eps and permeability mu constant per element:
  *
  *     du/dt = -sum_nu D^nu F(u) + L [ n.F - (n.F)* ],
  *
- * i.e. dE/dt = curl H + LIFT(Fscale fE), dH/dt = -curl E + LIFT(Fscale fH)
- * with the upwind flux of the paper's results section (Maxwell flux figure,
- * part a; H part by duality), dE = E- - E+, dH = H- - H+:
- *     fE = 1/2 [ -n x dH + alpha (n (n.dE) - dE) ]
- *     fH = 1/2 [  n x dE + alpha (n (n.dH) - dH) ],
- * perfectly conducting walls (E+ = -E-, H+ = H-) on every unmatched face, and
- * the five-stage fourth-order low-storage Runge-Kutta scheme of Carpenter and
- * Kennedy for time stepping ("including RK4 timestepping", Section 6).
+ * i.e. eps dE/dt = curl H + LIFT(Fscale fE), mu dH/dt = -curl E + LIFT(Fscale fH)
+ * with the upwind flux of the results section (Section 5, Maxwell flux
+ * figure, part a; H part by duality), dE = E- - E+, dH = H- - H+, and the
+ * impedances Z = sqrt(mu / eps), Y = 1 / Z of the own (-) and neighbour (+)
+ * element:
+ *     fE = [ -Z+ n x dH + alpha (n (n.dE) - dE) ] / (Z- + Z+)
+ *     fH = [  Y+ n x dE + alpha (n (n.dH) - dH) ] / (Y- + Y+),
+ * which for eps = mu = 1 is 1/2 [ -n x dH + alpha (n (n.dE) - dE) ] and
+ * 1/2 [ n x dE + alpha (n (n.dH) - dH) ].  A boundary face takes the
+ * exterior state E+ = a_E E-, H+ = a_H H- of its condition code (the boundary
+ * data of Section 2 on the domain boundary): (a_E, a_H) = (-1, 1) perfectly
+ * conducting, (1, -1) perfectly magnetic-conducting, (0, 0) absorbing; its
+ * exterior has the element's own material.  Time stepping is the
+ * five-stage fourth-order low-storage Runge-Kutta scheme of Carpenter and
+ * Kennedy (the paper times whole steps with their Runge-Kutta update
+ * included, Section 5).
  *
  * Reference element: nodal Lagrange basis of P_N on warp & blend nodes,
  * operators built from an orthonormal basis; reference tetrahedron
  * v0=(-1,-1,-1), v1=(1,-1,-1), v2=(-1,1,-1), v3=(-1,-1,1); element map
  * x = -(1+r+s+t)/2 X0 + (1+r)/2 X1 + (1+s)/2 X2 + (1+t)/2 X3 with X_i the
  * vertices EToV[k][i].  Node order: t lattice index outermost, then s, then r.
+ * Face f of an element has the local vertices {0,1,2}, {0,1,3}, {1,2,3},
+ * {0,2,3} for f = 0..3.
  *
  * Conventions for every call:
  *   - every function returns dg_status (0 = DG_OK, negative = error); nothing
@@ -32,10 +42,10 @@
  *   - "device pointer" arguments are HIP device allocations owned by the
  *     caller, "host pointer" arguments are ordinary host memory;
  *   - stream arguments are hipStream_t values passed as void* (NULL = the
- *     null stream); calls that take a stream are asynchronous on it and
- *     neither allocate nor synchronise;
- *   - the device that was current at dg_setup_mesh must be current when a
- *     problem's device calls are made.
+ *     null stream) of the problem's device; calls that take a stream are
+ *     asynchronous on it and neither allocate nor synchronise;
+ *   - a call on a problem makes the problem's device current for its
+ *     duration and restores the caller's current device before returning.
  */
 #ifndef DG_H_
 #define DG_H_
@@ -76,8 +86,14 @@ typedef enum {
 
 typedef struct dg_problem_s* dg_problem;  /* opaque; owns all mesh-derived device data */
 
-/* Mesh and discretisation (inputs of dg_setup_mesh).  Host pointers; the
- * library copies what it needs, the caller keeps ownership. */
+/* Boundary condition codes of dg_mesh_desc.face_bc (Section 2: boundary data
+ * on the domain boundary; the exterior state of a boundary face is built from
+ * the interior trace, see the header comment). */
+enum { DG_BC_CONDUCTING = 0, DG_BC_MAGNETIC = 1, DG_BC_ABSORBING = 2 };
+
+/* Mesh and discretisation (inputs of dg_setup_mesh): the tetrahedral mesh,
+ * polynomial space and flux of Section 2.  Host pointers; the library copies
+ * what it needs, the caller keeps ownership. */
 typedef struct {
   int32_t N;             /* polynomial order, 1..9                                */
   int32_t precision;     /* dg_precision                                          */
@@ -87,6 +103,13 @@ typedef struct {
   int64_t K;             /* number of tetrahedra, 1 .. 2^26-1                     */
   const int32_t* EToV;   /* host, K x 4 row-major, 0-based vertex ids; every
                             element must be positively oriented (J > 0)          */
+  const int8_t* face_bc; /* host, K x 4 (element, face) condition codes, read on
+                            boundary faces only (DG_BC_*); NULL: every boundary
+                            face is DG_BC_CONDUCTING                              */
+  const double* eps;     /* host, K permittivities (finite, > 0); NULL: all 1     */
+  const double* mu;      /* host, K permeabilities (finite, > 0); NULL: all 1     */
+  int32_t device;        /* HIP device ordinal the problem lives on; -1: the
+                            device current at dg_setup_mesh                       */
 } dg_mesh_desc;
 
 /* Layout of device state arrays (u, rhs, res).  A state array holds the six
@@ -110,21 +133,27 @@ typedef struct {
   int32_t variant;       /* kernel variant in use (dg_variant_name)               */
 } dg_info;
 
-/* Builds the reference element, geometry, connectivity and uploads them to
- * the current HIP device.  Synchronous.  *out receives a new handle on
- * success and is left untouched on error.
+/* Builds the reference element (Section 2: nodal basis, D = M^-1 S, face mass
+ * matrices, the lifting matrix L), the affine geometry and the face
+ * connectivity of Section 2.1, and uploads them to the problem's device.
+ * Synchronous.  *out receives a new handle on success and is left untouched
+ * on error.  Elements whose eps or mu differ from 1 select the material form
+ * of the kernels (FP64 and FP32 only).
  * Errors: DG_EINVAL (null pointer, K or Nv < 1, alpha not finite, precision
- * out of range), DG_EUNSUPPORTED (N outside 1..9, K >= 2^26, or one state
- * array -- 6 fields of K * Np values, each padded to 256 bytes -- of 2 GiB or
- * more: the kernels use 32-bit buffer offsets), DG_EMESH
- * (vertex id out of range, J <= 0, face multiplicity > 2), DG_EHIP/DG_ENOMEM. */
+ * out of range, a boundary face code outside 0..2, eps or mu not finite and
+ * positive, device out of range), DG_EUNSUPPORTED (N outside 1..9,
+ * K >= 2^26, one state array -- 6 fields of K * Np values, each padded to
+ * 256 bytes -- of 2 GiB or more: the kernels use 32-bit buffer offsets; eps
+ * or mu other than 1 with a split 16-bit precision), DG_EMESH (vertex id out
+ * of range, J <= 0, face multiplicity > 2), DG_EHIP/DG_ENOMEM. */
 dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out);
 
 /* Sizes and layout of a problem.  Errors: DG_EINVAL on null arguments. */
 dg_status dg_info_get(dg_problem p, dg_info* info);
 
-/* rhs <- du/dt evaluated at u (semi-discrete scheme, Section 2; flux as in
- * the header comment).  u, rhs: device pointers to state arrays in the
+/* rhs <- du/dt evaluated at u: the semi-discrete equation of Section 2, split
+ * as in Section 2.1 into local differentiation, flux gather and flux lifting
+ * (flux and boundary states as in the header comment).  u, rhs: device pointers to state arrays in the
  * problem's precision and layout; they must not overlap.  Asynchronous on
  * stream.  Only the K*Np entries of each field of rhs are written.
  * Errors: DG_EINVAL (null pointer, u == rhs, or a pointer not 16-byte
@@ -152,9 +181,12 @@ dg_status dg_set_variant(dg_problem p, int32_t v);
 dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, int32_t reps,
                       void* stream, double* ms);
 
-/* nsteps steps of the 5-stage low-storage RK4 scheme, in place:
- *   for each stage s: res <- A_s res + dt du/dt(u);  u <- u + B_s res,
- * A_1 = 0, so res needs no initial value.  u, res: device state arrays.
+/* nsteps steps of the 5-stage low-storage RK4 scheme (the time stepping
+ * that the paper's Section 5 times together with the operator), in place:
+ *   for each stage s: res <- A_s res + dt du/dt(u);  u <- u + B_s res.
+ * A_1 = 0 and the first stage of every step does not read res: its
+ * contents on entry, NaN or Inf bit patterns included, never enter the
+ * result.  u, res: device state arrays.
  * t is the start time; the perfectly conducting cavity has no time-dependent
  * data, so the stage times t + C_s dt do not enter the arithmetic.
  * Uses library-owned scratch allocated at setup; asynchronous on stream.
@@ -171,23 +203,26 @@ dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
  * A batch owns n problems (any mix of orders and sizes, one precision) and
  * steps them together: problems are grouped by order N and each Runge-Kutta
  * stage is one launch per group over all of its (problem, element tile)
- * pairs.  The paper notes that the host's launch rate only suffices when each
- * launch carries enough work; batching many small problems restores that. */
+ * pairs.  The paper notes (Section 4) that the host's launch rate only
+ * suffices when each launch carries enough work; batching many small problems
+ * restores that. */
 typedef struct dg_batch_s* dg_batch;
 
-/* Sets up descs[0..n-1] (host array) as one batch.  All problems must share
- * one precision and have a batched kernel (the "mfma" variant is built for
- * their order and precision).  Errors: as dg_setup_mesh (the message names
- * the problem), DG_EINVAL (n < 1, mixed precisions). */
+/* Sets up descs[0..n-1] (host array) as one batch: each problem as by
+ * dg_setup_mesh (Section 2's mesh, space and flux).  All problems must share
+ * one precision and one device, have eps = mu = 1 and have a batched kernel
+ * (the "mfma" variant is built for their order and precision).  Errors: as
+ * dg_setup_mesh (the message names the problem), DG_EINVAL (n < 1, mixed
+ * precisions or devices), DG_EUNSUPPORTED (materials, no batched kernel). */
 dg_status dg_setup_batch(int32_t n, const dg_mesh_desc* descs, dg_batch* out);
 
 /* Borrowed handle of problem i (for dg_info_get, dg_pack, dg_unpack,
  * dg_nodes, dg_rhs); it stays owned by the batch: never dg_destroy it. */
 dg_status dg_batch_problem(dg_batch b, int32_t i, dg_problem* p);
 
-/* nsteps LSERK steps of every problem, in place.  u, res, dt: host arrays of
- * n device pointers / time steps; u[i], res[i] are state arrays of problem
- * i.  mode 0: each step replays a graph of (5 stages x order groups) kernel
+/* nsteps LSERK steps (as dg_rk_step, res not read at the first stage) of
+ * every problem, in place.  u, res, dt: host arrays of n device pointers /
+ * time steps; u[i], res[i] are state arrays of problem i.  mode 0: each step replays a graph of (5 stages x order groups) kernel
  * launches, captured on the first call; mode 1: the same launches issued
  * directly; mode 2: one launch per problem and stage (dg_rk_step per
  * problem).  All modes give bitwise identical results.  Asynchronous on

@@ -35,7 +35,8 @@ dg_status dg_host_ref_nodes(int32_t N, double* r, double* s, double* t);
 dg_status dg_host_ref_operators(int32_t N, double* Dr, double* Ds, double* Dt,
                                 double* LIFT, int32_t* Fmask, double* Mf);
 
-/* Geometry and connectivity of a mesh (same validation as dg_setup_mesh):
+/* Geometry and connectivity of a mesh (Section 2.1; same validation as
+ * dg_setup_mesh; face_bc as dg_mesh_desc.face_bc, may be NULL):
  *   metric   K x 9   (rx, ry, rz, sx, sy, sz, tx, ty, tz)
  *   J        K
  *   face     K x 4 x 4 (nx, ny, nz, Fscale) per face
@@ -43,11 +44,12 @@ dg_status dg_host_ref_operators(int32_t N, double* Dr, double* Ds, double* Dt,
  *   vmapP    K x 4 x Nfp int64: k'*Np + i' of the neighbour node matching
  *            face node j of face f of element k, -1 on a wall face
  *   conn     K x 4 int32 packed neighbour code as used on the device:
- *            -1 on a wall, else nbr_elem * 32 + nbr_face * 6 + orient, where
- *            orient in 0..5 names how the shared face's vertices permute
+ *            nbr_elem * 32 + nbr_face * 6 + orient on an interior face, where
+ *            orient in 0..5 names how the shared face's vertices permute;
+ *            -1 - b on a boundary face with condition code b (DG_BC_*)
  * Any output pointer may be NULL.  Errors: as dg_setup_mesh. */
 dg_status dg_host_mesh(int32_t N, int64_t Nv, const double* VX, int64_t K,
-                       const int32_t* EToV, double* metric, double* J,
+                       const int32_t* EToV, const int8_t* face_bc, double* metric, double* J,
                        double* face, double* sJ, int64_t* vmapP, int32_t* conn);
 
 #ifdef __cplusplus

@@ -101,6 +101,7 @@ std::vector<T> cast_vec(const std::vector<double>& v) {
 
 void free_problem(dg_problem p) {
   if (!p) return;
+  DeviceGuard guard(p->device);
   hipFree(p->d_geo);
   hipFree(p->d_conn);
   hipFree(p->d_ops);
@@ -109,11 +110,36 @@ void free_problem(dg_problem p) {
   hipFree(p->d_frag);
   hipFree(p->d_frag16);
   hipFree(p->d_scratch);
+  hipFree(p->d_mat);
   delete p;
 }
 
+// Material records (see kMatStride) from per-element eps and mu (NULL: 1).
+std::vector<double> material_records(const HostMesh& hm, const double* eps, const double* mu, double alpha) {
+  const int64_t K = hm.K;
+  auto e_of = [&](int64_t k) { return eps ? eps[k] : 1.0; };
+  auto m_of = [&](int64_t k) { return mu ? mu[k] : 1.0; };
+  std::vector<double> rec(size_t(K) * dgd::kMatStride);
+  for (int64_t k = 0; k < K; ++k) {
+    double* r = &rec[size_t(k) * dgd::kMatStride];
+    const double ek = e_of(k), mk = m_of(k), zm = std::sqrt(mk / ek);
+    r[0] = 1.0 / ek;
+    r[1] = 1.0 / mk;
+    for (int f = 0; f < 4; ++f) {
+      const int32_t c = hm.conn[size_t(k) * 4 + f];
+      const double zp = c >= 0 ? std::sqrt(m_of(c >> 5) / e_of(c >> 5)) : zm;
+      const double fsc = hm.face[(size_t(k) * 4 + f) * 4 + 3];
+      r[2 + 4 * f] = fsc * zp / (zm + zp) / ek;
+      r[3 + 4 * f] = fsc * (1.0 / zp) / (1.0 / zm + 1.0 / zp) / mk;
+      r[4 + 4 * f] = alpha / zp;
+      r[5 + 4 * f] = alpha * zp;
+    }
+  }
+  return rec;
+}
+
 template <typename T>
-dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
+dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm, const std::vector<double>& mat) {
   const int Np = re.Np, NF = 4 * re.Nfp;
   const int64_t K = hm.K;
   // Geometry records.
@@ -151,6 +177,11 @@ dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm) {
   std::vector<int32_t> fm(re.fmask.begin(), re.fmask.end());
   DG_HIP(hipMemcpy(p->d_fmask, fm.data(), fm.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload fmask");
   DG_HIP(hipMemset(p->d_scratch, 0, size_t(p->state_elems) * sizeof(T)), "clear scratch");
+  if (!mat.empty()) {
+    const std::vector<T> mt = cast_vec<T>(mat);
+    DG_HIP(hipMalloc(&p->d_mat, mt.size() * sizeof(T)), "hipMalloc(material)");
+    DG_HIP(hipMemcpy(p->d_mat, mt.data(), mt.size() * sizeof(T), hipMemcpyHostToDevice), "upload material");
+  }
 
   // MFMA A-fragments: row block ib, depth step kg, lane l holds
   // Op[16 ib + l % 16][depth column of (kg, l / 16)] with Op = [Dr|Ds|Dt|LIFT],
@@ -220,6 +251,7 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   a.rhs = rhs;
   a.geo = p->d_geo;
   a.conn = p->d_conn;
+  a.mat = p->d_mat;
   a.ops = p->d_ops;
   a.ops_frag = p->d_frag;
   a.ops_frag16 = p->d_frag16;
@@ -271,11 +303,12 @@ dg_status dg_host_ref_operators(int32_t N, double* Dr, double* Ds, double* Dt, d
   return DG_OK;
 }
 
-dg_status dg_host_mesh(int32_t N, int64_t Nv, const double* VX, int64_t K, const int32_t* EToV, double* metric,
-                       double* J, double* face, double* sJ, int64_t* vmapP, int32_t* conn) {
+dg_status dg_host_mesh(int32_t N, int64_t Nv, const double* VX, int64_t K, const int32_t* EToV,
+                       const int8_t* face_bc, double* metric, double* J, double* face, double* sJ, int64_t* vmapP,
+                       int32_t* conn) {
   clear_error();
   HostMesh hm;
-  dg_status st = build_mesh(N, Nv, VX, K, EToV, hm);
+  dg_status st = build_mesh(N, Nv, VX, K, EToV, face_bc, hm);
   if (st != DG_OK) return st;
   const RefElement* re = ref_element(N);
   if (!re) return fail(DG_EUNSUPPORTED, "reference element construction failed");
@@ -305,8 +338,22 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   if (desc->precision < DG_FP64 || desc->precision > DG_F16X2) return fail(DG_EINVAL, "precision out of range");
   if (!std::isfinite(desc->alpha)) return fail(DG_EINVAL, "alpha must be finite");
   if (desc->N < 1 || desc->N > kMaxOrder) return fail(DG_EUNSUPPORTED, "order N must be in 1..9");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+  if (desc->device < -1 || desc->device >= ndev) return fail(DG_EINVAL, "device out of range");
+  bool material = false;
+  if (desc->K >= 1)
+    for (const double* v : {desc->eps, desc->mu})
+      if (v)
+        for (int64_t k = 0; k < desc->K; ++k) {
+          if (!(std::isfinite(v[k]) && v[k] > 0.0))
+            return fail(DG_EINVAL, "eps and mu must be finite and positive (element " + std::to_string(k) + ")");
+          if (v[k] != 1.0) material = true;
+        }
+  if (material && desc->precision != DG_FP64 && desc->precision != DG_FP32)
+    return fail(DG_EUNSUPPORTED, "eps or mu other than 1 needs precision FP64 or FP32");
   HostMesh hm;
-  dg_status st = build_mesh(desc->N, desc->Nv, desc->VX, desc->K, desc->EToV, hm);
+  dg_status st = build_mesh(desc->N, desc->Nv, desc->VX, desc->K, desc->EToV, desc->face_bc, hm);
   if (st != DG_OK) return st;
   const RefElement* re = ref_element(desc->N);
   if (!re) return fail(DG_EUNSUPPORTED, "reference element construction failed");
@@ -319,6 +366,11 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
       return fail(DG_EUNSUPPORTED, "state array of 2 GiB or more (K * Np too large for this precision)");
   }
 
+  // Validation is done: from here on the problem's device is current.
+  int dev = desc->device;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(DG_EHIP, "hipGetDevice failed");
+  DeviceGuard guard(dev);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
   auto p = new dg_problem_s();
   p->N = desc->N;
   p->Np = re->Np;
@@ -332,25 +384,36 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   p->fs = ((p->K * p->Np + align - 1) / align) * align;
   p->state_elems = 6 * p->fs;
   p->n_boundary = hm.n_boundary;
-  p->dt_cfl1 = 2.0 / ((desc->N + 1.0) * (desc->N + 1.0) * hm.max_fscale);
+  p->material = material;
+  // dt ~ dx / N^2 (Section 3's time-step restriction): 2 / ((N+1)^2 max Fscale)
+  // for eps = mu = 1; with materials the wave speed 1 / sqrt(eps mu) of the
+  // fastest element scales it.
+  double cmax = 1.0;
+  if (material) {
+    cmax = 0.0;
+    for (int64_t k = 0; k < desc->K; ++k)
+      cmax = std::max(cmax, 1.0 / std::sqrt((desc->eps ? desc->eps[k] : 1.0) * (desc->mu ? desc->mu[k] : 1.0)));
+  }
+  p->dt_cfl1 = 2.0 / ((desc->N + 1.0) * (desc->N + 1.0) * hm.max_fscale * cmax);
   // Default kernel: the matrix-core variant where it is built, else the vector one.
   p->variant = dgd::kVariantMfma;
-  p->ks = dgd::kernels(desc->N, desc->precision, p->variant);
+  p->ks = dgd::kernels(desc->N, desc->precision, p->variant, material);
   if (!p->ks.rhs) {
     p->variant = dgd::kVariantValu;
-    p->ks = dgd::kernels(desc->N, desc->precision, p->variant);
+    p->ks = dgd::kernels(desc->N, desc->precision, p->variant, material);
   }
   if (!p->ks.rhs) {
     delete p;
     return fail(DG_EUNSUPPORTED, "no kernel for this order and precision");
   }
   p->tile = p->ks.tile;
-  hipGetDevice(&p->device);
+  p->device = dev;
   p->verts.resize(size_t(p->K) * 12);
   for (int64_t k = 0; k < p->K; ++k)
     for (int v = 0; v < 4; ++v)
       for (int d = 0; d < 3; ++d) p->verts[size_t(k) * 12 + v * 3 + d] = desc->VX[3 * int64_t(desc->EToV[4 * k + v]) + d];
-  st = (p->precision == DG_FP64) ? upload<double>(p, *re, hm) : upload<float>(p, *re, hm);
+  const std::vector<double> mat = material ? material_records(hm, desc->eps, desc->mu, desc->alpha) : std::vector<double>();
+  st = (p->precision == DG_FP64) ? upload<double>(p, *re, hm, mat) : upload<float>(p, *re, hm, mat);
   if (st != DG_OK) {
     free_problem(p);
     return st;
@@ -386,7 +449,7 @@ dg_status dg_set_variant(dg_problem p, int32_t v) {
   clear_error();
   if (!p) return fail(DG_EINVAL, "null problem");
   if (v < 0 || v >= dgd::kVariantCount) return fail(DG_EINVAL, "variant out of range");
-  dgd::KernelSet k = dgd::kernels(p->N, p->precision, v);
+  dgd::KernelSet k = dgd::kernels(p->N, p->precision, v, p->material);
   if (!k.rhs) return fail(DG_EUNSUPPORTED, "variant not built for this order/precision");
   p->variant = v;
   p->ks = k;
@@ -400,6 +463,8 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream) {
   if (u == rhs) return fail(DG_EINVAL, "u and rhs must not alias");
   if (!aligned16(u) || !aligned16(rhs)) return fail(DG_EINVAL, "state arrays must be 16-byte aligned");
   if (!p->ks.rhs) return fail(DG_EUNSUPPORTED, "no kernel for this order/precision");
+  DeviceGuard guard(p->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
   hipError_t e = p->ks.rhs(rhs_args(p, u, rhs), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
   return DG_OK;
@@ -410,6 +475,8 @@ dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, in
   clear_error();
   if (!p || !u || !rhs || !ms) return fail(DG_EINVAL, "null argument");
   if (reps < 1 || warmup < 0) return fail(DG_EINVAL, "need reps >= 1 and warmup >= 0");
+  DeviceGuard guard(p->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (int32_t i = 0; i < warmup; ++i) {
     dg_status st = dg_rhs(p, u, rhs, stream);
@@ -445,6 +512,8 @@ dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int3
   if (!aligned16(u) || !aligned16(res)) return fail(DG_EINVAL, "state arrays must be 16-byte aligned");
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  DeviceGuard guard(p->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t bytes = size_t(p->state_elems) * p->elem_bytes;
   if (p->ks.rk) {
@@ -493,6 +562,8 @@ dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int3
 dg_status dg_pack(dg_problem p, const double* host_u, void* dev_u, void* stream) {
   clear_error();
   if (!p || !host_u || !dev_u) return fail(DG_EINVAL, "null argument");
+  DeviceGuard guard(p->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = p->K * p->Np;
   if (p->precision == DG_FP64) {
@@ -513,6 +584,8 @@ dg_status dg_pack(dg_problem p, const double* host_u, void* dev_u, void* stream)
 dg_status dg_unpack(dg_problem p, const void* dev_u, double* host_u, void* stream) {
   clear_error();
   if (!p || !host_u || !dev_u) return fail(DG_EINVAL, "null argument");
+  DeviceGuard guard(p->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = p->K * p->Np;
   if (p->precision == DG_FP64) {

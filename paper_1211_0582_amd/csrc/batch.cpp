@@ -40,7 +40,7 @@ struct dg_batch_s {
   std::vector<dgd::BatchProblem> table;
   bool table_valid = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // step starting at parity 0 / 1
-  int precision = 0;
+  int precision = 0, device = 0;
   int stream_out = 0;  // streaming stores: the step's state arrays exceed the last-level cache
 };
 
@@ -58,6 +58,7 @@ dg_status hip_err(hipError_t e, const char* what) {
 
 void free_batch(dg_batch b) {
   if (!b) return;
+  DeviceGuard guard(b->problems.empty() ? b->device : b->problems[0]->device);
   for (int i = 0; i < 2; ++i)
     if (b->graph[i]) hipGraphExecDestroy(b->graph[i]);
   for (auto& g : b->groups) hipFree(g.d_items);
@@ -122,14 +123,19 @@ extern "C" {
 dg_status dg_setup_batch(int32_t n, const dg_mesh_desc* descs, dg_batch* out) {
   clear_error();
   if (n < 1 || !descs || !out) return fail(DG_EINVAL, "need n >= 1 and non-null descs/out");
-  for (int32_t i = 1; i < n; ++i)
+  for (int32_t i = 1; i < n; ++i) {
     if (descs[i].precision != descs[0].precision) return fail(DG_EINVAL, "all problems of a batch share one precision");
+    if (descs[i].device != descs[0].device) return fail(DG_EINVAL, "all problems of a batch share one device");
+  }
   auto b = new dg_batch_s();
   b->precision = descs[0].precision;
   for (int32_t i = 0; i < n; ++i) {
     dg_problem p = nullptr;
     dg_status st = dg_setup_mesh(&descs[i], &p);
-    if (st == DG_OK && !p->ks.batch) {
+    if (st == DG_OK && p->material) {
+      dg_destroy(p);
+      st = fail(DG_EUNSUPPORTED, "batched problems must have eps = mu = 1");
+    } else if (st == DG_OK && !p->ks.batch) {
       // the batched stage exists for the matrix-core kernel only
       if (dg_set_variant(p, dgd::kVariantMfma) != DG_OK || !p->ks.batch) {
         dg_destroy(p);
@@ -143,6 +149,8 @@ dg_status dg_setup_batch(int32_t n, const dg_mesh_desc* descs, dg_batch* out) {
     }
     b->problems.push_back(p);
   }
+  b->device = b->problems[0]->device;
+  DeviceGuard guard(b->device);
   // One step cycles through every problem's u, res and second state buffer.
   int64_t step_bytes = 0;
   for (dg_problem p : b->problems) step_bytes += 3 * p->state_elems * p->elem_bytes;
@@ -210,6 +218,8 @@ dg_status dg_rk_step_batch(dg_batch b, void* const* u, void* const* res, const d
       return fail(DG_EINVAL, "problem " + std::to_string(i) + ": state arrays must be 16-byte aligned");
     if (!std::isfinite(dt[i])) return fail(DG_EINVAL, "problem " + std::to_string(i) + ": dt not finite");
   }
+  DeviceGuard guard(b->device);
+  if (guard.err != hipSuccess) return hip_err(guard.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (mode == 2) {  // one launch per problem and stage
     for (size_t i = 0; i < n; ++i) {

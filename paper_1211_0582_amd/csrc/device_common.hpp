@@ -12,12 +12,35 @@ namespace dgd {
 //   [9+4f .. 12+4f] face f: nx ny nz Fscale
 constexpr int kGeoStride = 25;
 
+// Per-element material record (problems whose eps or mu differ from 1):
+// 18 scalars,
+//   [0] 1 / eps, [1] 1 / mu,
+//   [2+4f .. 5+4f] face f: Fscale Z+ / ((Z- + Z+) eps), Fscale Y+ / ((Y- + Y+) mu),
+//                  alpha / Z+, alpha Z+
+// with Z = sqrt(mu / eps), Y = 1 / Z of the own (-) and neighbour (+)
+// element (a boundary face's exterior has the own material).  With these the
+// material flux is fE = s_E [ -n x dH + a_E (n (n.dE) - dE) ] and
+// fH = s_H [ n x dE + a_H (n (n.dH) - dH) ], already divided by eps / mu; for
+// eps = mu = 1 the record reproduces the vacuum flux exactly.
+constexpr int kMatStride = 18;
+
+// Exterior-state factors of a face from its connectivity word c: interior
+// (c >= 0) reads the neighbour trace (1, 1); a boundary face (c = -1 - b)
+// mirrors the own trace, E+ = s_E E-, H+ = s_H H-: conducting (-1, 1),
+// magnetic-conducting (1, -1), absorbing (0, 0).
+template <typename T>
+__device__ __host__ inline void exterior_factors(int32_t c, T& sE, T& sH) {
+  sE = c >= 0 ? T(1) : (c == -1 ? T(-1) : (c == -2 ? T(1) : T(0)));
+  sH = c >= -1 ? T(1) : (c == -2 ? T(-1) : T(0));
+}
+
 // Arguments of one right-hand-side evaluation (or one fused Runge-Kutta stage).
 struct RhsArgs {
   const void* u;          // state, [6][field_stride], element-major inside a field
   void* rhs;              // output, same layout (right-hand-side mode)
   const void* geo;        // K x kGeoStride
-  const int32_t* conn;    // K x 4, -1 wall, else nbr*32 + nbr_face*6 + orient
+  const int32_t* conn;    // K x 4, nbr*32 + nbr_face*6 + orient, or -1 - bc on a boundary face
+  const void* mat;        // K x kMatStride material records, or nullptr (eps = mu = 1)
   const void* ops;        // Dr^T, Ds^T, Dt^T (Np x Np each, [j][i]), LIFT^T (4Nfp x Np, [m][i])
   const void* ops_frag;   // [Dr|Ds|Dt|LIFT] as 16x4 MFMA A-fragments [row block][depth step][lane]
   const void* ops_frag16; // same operator split into 16-bit heads and tails, 16x16x16 A-fragments
@@ -59,7 +82,8 @@ struct BatchArgs {
 };
 using BatchLauncher = hipError_t (*)(const BatchArgs&, hipStream_t);
 
-// Arguments of one LSERK stage update: res <- a res + dt rhs; u <- u + b res.
+// Arguments of one LSERK stage update: res <- a res + dt rhs; u <- u + b res
+// (res not read when a = 0).
 struct UpdateArgs {
   void* u;
   void* res;
@@ -83,9 +107,10 @@ struct KernelSet {
   BatchLauncher batch = nullptr;  // batched fused stage (matrix-core variant)
 };
 
-// Kernels for order N (1..9), precision (dg_precision) and variant;
-// rhs == nullptr when the combination is not built.
-KernelSet kernels(int N, int precision, int variant);
+// Kernels for order N (1..9), precision (dg_precision), variant and flux
+// form (material: per-element eps, mu); rhs == nullptr when the combination
+// is not built.
+KernelSet kernels(int N, int precision, int variant, bool material);
 
 hipError_t launch_update(const UpdateArgs& a, int precision, hipStream_t s);
 

@@ -18,6 +18,9 @@ const char* error_text();
 
 constexpr int kMaxOrder = 9;
 
+// Boundary condition codes of dg_mesh_desc.face_bc.
+constexpr int kBcConducting = 0, kBcMagnetic = 1, kBcAbsorbing = 2;
+
 inline int n_p(int N) { return (N + 1) * (N + 2) * (N + 3) / 6; }
 inline int n_fp(int N) { return (N + 1) * (N + 2) / 2; }
 
@@ -69,12 +72,13 @@ struct HostMesh {
   std::vector<double> J;        // K
   std::vector<double> face;     // K x 4 x 4 (nx, ny, nz, Fscale)
   std::vector<double> sJ;       // K x 4
-  std::vector<int32_t> conn;    // K x 4
+  std::vector<int32_t> conn;    // K x 4: nbr*32 + nbr_face*6 + orient, or -1 - bc on a boundary face
   double max_fscale = 0.0;
   int64_t n_boundary = 0;
 };
 
+// face_bc: K x 4 condition codes read on boundary faces only (NULL: all 0).
 dg_status build_mesh(int N, int64_t Nv, const double* VX, int64_t K, const int32_t* EToV,
-                     HostMesh& out);
+                     const int8_t* face_bc, HostMesh& out);
 
 }  // namespace dgh

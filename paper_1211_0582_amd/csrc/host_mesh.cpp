@@ -9,10 +9,12 @@
 // Fscale = sJ / J.
 //
 // Connectivity: faces are keyed by their sorted global vertex triple and
-// matched by sorting; an unmatched face is a perfectly conducting wall.  A
-// matched face stores the neighbour element, its local face and the
-// orientation code (which of the six slot permutations maps our face's
-// vertices to the neighbour's), all the flux gather needs to find u+.
+// matched by sorting.  A matched face stores the neighbour element, its local
+// face and the orientation code (which of the six slot permutations maps our
+// face's vertices to the neighbour's), all the flux gather needs to find u+.
+// An unmatched face is a boundary face and stores -1 - b, b its boundary
+// condition code (the boundary data of Section 2 on the domain boundary):
+// 0 perfectly conducting, 1 perfectly magnetic-conducting, 2 absorbing.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,7 +35,8 @@ dg_status fail(dg_status s, const std::string& msg) {
   return s;
 }
 
-dg_status build_mesh(int N, int64_t Nv, const double* VX, int64_t K, const int32_t* EToV, HostMesh& out) {
+dg_status build_mesh(int N, int64_t Nv, const double* VX, int64_t K, const int32_t* EToV, const int8_t* face_bc,
+                     HostMesh& out) {
   if (!VX || !EToV) return fail(DG_EINVAL, "VX and EToV must be non-null");
   if (Nv < 4 || K < 1) return fail(DG_EINVAL, "need Nv >= 4 and K >= 1");
   if (N < 1 || N > kMaxOrder) return fail(DG_EUNSUPPORTED, "order N must be in 1..9");
@@ -147,6 +150,12 @@ dg_status build_mesh(int N, int64_t Nv, const double* VX, int64_t K, const int32
         out.conn[size_t(k1) * 4 + f1] = k2 * 32 + f2 * 6 + code;
       }
     } else {
+      const int k1 = keys[i].elem_face / 4, f1 = keys[i].elem_face % 4;
+      const int b = face_bc ? int(face_bc[size_t(k1) * 4 + f1]) : kBcConducting;
+      if (b < kBcConducting || b > kBcAbsorbing)
+        return fail(DG_EINVAL, "boundary face " + std::to_string(f1) + " of element " + std::to_string(k1) +
+                                   " has condition code " + std::to_string(b) + " (must be 0, 1 or 2)");
+      out.conn[size_t(k1) * 4 + f1] = -1 - b;
       ++nb;
     }
     i = j;

@@ -9,7 +9,7 @@
 
 namespace dgd {
 
-#define DG_DECL(n) KernelSet kernels_n##n(int precision, int variant);
+#define DG_DECL(n) KernelSet kernels_n##n(int precision, int variant, bool material);
 DG_DECL(1)
 DG_DECL(2)
 DG_DECL(3)
@@ -21,28 +21,31 @@ DG_DECL(8)
 DG_DECL(9)
 #undef DG_DECL
 
-KernelSet kernels(int N, int p, int v) {
+KernelSet kernels(int N, int p, int v, bool m) {
   switch (N) {
-    case 1: return kernels_n1(p, v);
-    case 2: return kernels_n2(p, v);
-    case 3: return kernels_n3(p, v);
-    case 4: return kernels_n4(p, v);
-    case 5: return kernels_n5(p, v);
-    case 6: return kernels_n6(p, v);
-    case 7: return kernels_n7(p, v);
-    case 8: return kernels_n8(p, v);
-    case 9: return kernels_n9(p, v);
+    case 1: return kernels_n1(p, v, m);
+    case 2: return kernels_n2(p, v, m);
+    case 3: return kernels_n3(p, v, m);
+    case 4: return kernels_n4(p, v, m);
+    case 5: return kernels_n5(p, v, m);
+    case 6: return kernels_n6(p, v, m);
+    case 7: return kernels_n7(p, v, m);
+    case 8: return kernels_n8(p, v, m);
+    case 9: return kernels_n9(p, v, m);
     default: return KernelSet{};
   }
 }
 
+// a = 0 (the first stage) does not read res, so its contents on entry never
+// enter the update.
 template <typename T>
 __global__ __launch_bounds__(256) void lserk_update_kernel(T* __restrict__ u, T* __restrict__ res,
                                                            const T* __restrict__ rhs, int64_t n, int64_t fs,
                                                            T a, T b, T dt) {
   const int64_t off = int64_t(blockIdx.y) * fs;
+  const bool first = a == T(0);
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    const T r = a * res[off + i] + dt * rhs[off + i];
+    const T r = first ? dt * rhs[off + i] : a * res[off + i] + dt * rhs[off + i];
     res[off + i] = r;
     u[off + i] += b * r;
   }

@@ -19,6 +19,8 @@ struct dg_problem_s {
   void* d_frag = nullptr;     // MFMA A-fragments of [Dr|Ds|Dt|LIFT]
   void* d_frag16 = nullptr;   // the same split into 16-bit heads and tails (split precisions)
   void* d_scratch = nullptr;  // rhs buffer (unfused stepping) / second state buffer (fused)
+  void* d_mat = nullptr;      // material records (K x kMatStride), nullptr for eps = mu = 1
+  bool material = false;
   std::vector<double> verts;  // K x 4 x 3 vertex coordinates (for dg_nodes)
   int variant = 0;
   dgd::KernelSet ks;
@@ -36,6 +38,22 @@ constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;
 
 // The kernels write state arrays with 16-byte stores.
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Makes `device` current for the guard's lifetime and restores the caller's
+// current device afterwards (every call on a problem runs on its device).
+struct DeviceGuard {
+  int prev = -1, dev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int d) : dev(d) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+  }
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
 
 // Kernel arguments of a right-hand-side evaluation of p.
 dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs);

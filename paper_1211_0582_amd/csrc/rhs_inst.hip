@@ -14,8 +14,10 @@
 namespace dgd {
 
 namespace {
+// material: per-element eps and mu (FP64 and FP32; the vector kernel handles
+// both flux forms at run time).
 template <typename T>
-KernelSet make(int variant) {
+KernelSet make(int variant, bool material) {
   constexpr int N = DG_ORDER;
   KernelSet k;
   if (variant == kVariantValu) {
@@ -23,9 +25,14 @@ KernelSet make(int variant) {
     k.tile = valu_tile<N>();
   } else if (variant == kVariantMfma) {
     if constexpr (mfma_supported<N, T>()) {
-      k.rhs = &launch_rhs_mfma<N, T>;
-      k.rk = &launch_rk_mfma<N, T>;
-      k.batch = &launch_rk_mfma_batch<N, T>;
+      if (material) {
+        k.rhs = &launch_rhs_mfma<N, T, 0, true>;
+        k.rk = &launch_rk_mfma<N, T, 0, true>;
+      } else {
+        k.rhs = &launch_rhs_mfma<N, T>;
+        k.rk = &launch_rk_mfma<N, T>;
+        k.batch = &launch_rk_mfma_batch<N, T>;
+      }
       k.tile = 16;
       k.frag_count = MfmaShape<N>::frag_count;
     }
@@ -33,12 +40,13 @@ KernelSet make(int variant) {
   return k;
 }
 
-// Split 16-bit contraction (FP32 state): matrix-core variants only.
+// Split 16-bit contraction (FP32 state): matrix-core variants only, vacuum
+// flux only.
 template <int MIX>
-KernelSet make_mixed(int variant) {
+KernelSet make_mixed(int variant, bool material) {
   constexpr int N = DG_ORDER;
   KernelSet k;
-  if (variant == kVariantMfma) {
+  if (variant == kVariantMfma && !material) {
     if constexpr (mfma_supported<N, float>()) {
       k.rhs = &launch_rhs_mfma<N, float, MIX>;
       k.rk = &launch_rk_mfma<N, float, MIX>;
@@ -51,16 +59,16 @@ KernelSet make_mixed(int variant) {
 }  // namespace
 
 // precision: 0 FP64, 1 FP32, 2 BF16x3, 3 FP16x3, 4 BF16, 5 FP16, 6 BF16x2, 7 FP16x2
-KernelSet DG_CAT(kernels_n, DG_ORDER)(int precision, int variant) {
+KernelSet DG_CAT(kernels_n, DG_ORDER)(int precision, int variant, bool material) {
   switch (precision) {
-    case 0: return make<double>(variant);
-    case 1: return make<float>(variant);
-    case 2: return make_mixed<3>(variant);
-    case 3: return make_mixed<6>(variant);
-    case 4: return make_mixed<1>(variant);
-    case 5: return make_mixed<4>(variant);
-    case 6: return make_mixed<2>(variant);
-    case 7: return make_mixed<5>(variant);
+    case 0: return make<double>(variant, material);
+    case 1: return make<float>(variant, material);
+    case 2: return make_mixed<3>(variant, material);
+    case 3: return make_mixed<6>(variant, material);
+    case 4: return make_mixed<1>(variant, material);
+    case 5: return make_mixed<4>(variant, material);
+    case 6: return make_mixed<2>(variant, material);
+    case 7: return make_mixed<5>(variant, material);
     default: return KernelSet{};
   }
 }

@@ -19,8 +19,8 @@
 //  * The tile's fields sit in LDS as [c][j][e] (16 elements fastest), read in
 //    B-fragment layout; X_d is formed in registers.
 //  * The flux is evaluated once per (element, face node) by all lanes:
-//    the neighbour trace comes through the orientation table (a wall reads
-//    the own node and mirrors it), and the fluxes are staged in LDS in
+//    the neighbour trace comes through the orientation table (a boundary
+//    face reads the own node and mirrors it), and the fluxes are staged in LDS in
 //    B-fragment order over the field tile for the LIFT MFMAs -- the facial
 //    buffer of the paper's split pipeline never reaches HBM.
 //  * Epilogue: accumulators go through LDS to coalesced 16-byte stores; in
@@ -174,15 +174,18 @@ __device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t vof
 }
 
 // State shared by the two waves of a workgroup.
-template <int N, typename T, bool HALF = false>
+template <int N, typename T, bool HALF = false, bool MAT = false>
 struct MfmaTile {
   using S = MfmaShape<N>;
   static constexpr bool kHalf = HALF;
+  static constexpr int kFaceRec = MAT ? 8 : 4;
   T su[S::tile(HALF)];                // fields [c][j][e], then fluxes [c][m][e], then output
   int16_t fmask[S::NF];
   alignas(16) uint8_t nbr[(4 * 24 * S::Nfp + 15) / 16 * 16];
   int32_t code[16 * 4];               // face codes of the tile's elements
-  T face[16 * 4 * 4];                 // nx, ny, nz, Fscale / 2 per (element, face)
+  // per (element, face): nx, ny, nz, Fscale / 2 (vacuum), or
+  // nx, ny, nz, s_E, s_H, a_E, a_H of the material record
+  T face[16 * 4 * kFaceRec];
 };
 
 // Where the flux work of a tile runs relative to the contraction.  Flux
@@ -557,7 +560,11 @@ constexpr bool lift_split() {
 // MIX = 0: contraction in T on 16x16x4 MFMAs; MIX = 1..3: T = float with the
 // contraction split in BF16 (NPROD = MIX); MIX = 4..6: split in FP16
 // (NPROD = MIX - 3).
-template <int N, typename T, bool RK, int MIX>
+//
+// MAT: per-element eps and mu (material record, see kMatStride): the metric
+// of the volume operand is scaled by 1 / eps (E role) or 1 / mu (H role), and
+// the flux takes the record's per-face scales and upwind weights.
+template <int N, typename T, bool RK, int MIX, bool MAT = false>
 __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
@@ -567,7 +574,8 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   constexpr int WPT = waves_per_tile<N, T, MIX>();
   constexpr int NT = 64 * WPT;        // lanes per tile
   constexpr int RBW = RB * 2 / WPT;   // row blocks per wave
-  __shared__ MfmaTile<N, T, LIFT_HALF> t;
+  __shared__ MfmaTile<N, T, LIFT_HALF, MAT> t;
+  constexpr int FREC = MfmaTile<N, T, LIFT_HALF, MAT>::kFaceRec;
 
   const int64_t fs = a.fs;
   const int tid = threadIdx.x;
@@ -600,6 +608,11 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
 #pragma unroll
     for (int i = 0; i < 9; ++i) mr[i] = buf_load<T>(rg, go, i * sz);
   }
+  // Material: the role's 1 / eps or 1 / mu, and the face scales and weights.
+  T mscale = T(1);
+  T fmr[4] = {T(0), T(0), T(0), T(0)};
+  const __amdgpu_buffer_rsrc_t rmat = make_rsrc(a.mat, MAT ? uint32_t(a.K) * kMatStride * sz : 0u);
+  if constexpr (MAT) mscale = buf_load<T>(rmat, live ? uint32_t(ke * kMatStride + h) * sz : kOob, 0);
   // Face records and connectivity codes (lanes 0..63: 16 elements x 4 faces).
   T fc[4];
   int32_t cf;
@@ -612,6 +625,11 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     cf = lv ? cf : -1;
 #pragma unroll
     for (int i = 0; i < 4; ++i) fc[i] = buf_load<T>(rg, go, i * sz);
+    if constexpr (MAT) {
+      const uint32_t mo = lv ? uint32_t((k0 + ee) * kMatStride + 2 + 4 * f) * sz : kOob;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fmr[i] = buf_load<T>(rmat, mo, i * sz);
+    }
   }
   // Tables (indices clamped so the loads need no branch); 16-byte loads for
   // the orientation table (its device copy is padded to a multiple of 16 B).
@@ -645,10 +663,19 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // LDS: face records, codes, tables, then the fields [c][j][e].
   if (tid < 64) {
     t.code[tid] = cf;
-    t.face[4 * tid + 0] = fc[0];
-    t.face[4 * tid + 1] = fc[1];
-    t.face[4 * tid + 2] = fc[2];
-    t.face[4 * tid + 3] = T(0.5) * fc[3];
+    t.face[FREC * tid + 0] = fc[0];
+    t.face[FREC * tid + 1] = fc[1];
+    t.face[FREC * tid + 2] = fc[2];
+    if constexpr (MAT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t.face[FREC * tid + 3 + i] = fmr[i];
+    } else {
+      t.face[FREC * tid + 3] = T(0.5) * fc[3];
+    }
+  }
+  if constexpr (MAT) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) mr[i] *= mscale;
   }
 #pragma unroll
   for (int it = 0; it < kFmaskIters; ++it) {
@@ -693,7 +720,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       const int ee = pr & 15, m = pr >> 4;
       const int f = m / Nfp, jj = m - f * Nfp;
       const int32_t cf = (pr < kPairs) ? t.code[4 * ee + f] : -1;
-      // interior: neighbour node; wall: own node (mirror applied below); dead: zero
+      // interior: neighbour node; boundary: own node (mirror applied below); dead: zero
       uint32_t vo = kOob;
       if (pr < kPairs && ee < ne)
         vo = uint32_t(cf >= 0 ? int64_t(cf >> 5) * Np + t.nbr[(f * 24 + (cf & 31)) * Nfp + jj]
@@ -708,23 +735,40 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     if (pr < kPairs) {
       const int f = m / Nfp;
       const int own = t.fmask[m];
-      const T se = t.code[4 * ee + f] < 0 ? T(-1) : T(1);  // wall: E+ = -E-, H+ = H-
+      // exterior state E+ = se g, H+ = sh g with g the gathered trace
+      // (interior: the neighbour's, se = sh = 1; boundary: the own one)
+      const int32_t cd = t.code[4 * ee + f];
       T d[6];
+      {
+        const T se = cd >= 0 ? T(1) : (cd == -1 ? T(-1) : (cd == -2 ? T(1) : T(0)));
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const T em = t.su[(c * Np4 + own) * TS + ee];
-        d[c] = c < 3 ? em - se * gx[it][c] : em - gx[it][c];
+        for (int c = 0; c < 3; ++c) d[c] = t.su[(c * Np4 + own) * TS + ee] - se * gx[it][c];
       }
-      const T* fr = &t.face[4 * (4 * ee + f)];
-      const T nx = fr[0], ny = fr[1], nz = fr[2], sc = fr[3];
+      {
+        const T sh = cd >= -1 ? T(1) : (cd == -2 ? T(-1) : T(0));
+#pragma unroll
+        for (int c = 3; c < 6; ++c) d[c] = t.su[(c * Np4 + own) * TS + ee] - sh * gx[it][c];
+      }
+      const T* fr = &t.face[FREC * (4 * ee + f)];
+      const T nx = fr[0], ny = fr[1], nz = fr[2];
+      T scE, scH, aE, aH;
+      if constexpr (MAT) {
+        scE = fr[3];
+        scH = fr[4];
+        aE = fr[5];
+        aH = fr[6];
+      } else {
+        scE = scH = fr[3];
+        aE = aH = alpha;
+      }
       const T ndE = nx * d[0] + ny * d[1] + nz * d[2];
       const T ndH = nx * d[3] + ny * d[4] + nz * d[5];
-      fl[it][0] = sc * (-(ny * d[5] - nz * d[4]) + alpha * (nx * ndE - d[0]));
-      fl[it][1] = sc * (-(nz * d[3] - nx * d[5]) + alpha * (ny * ndE - d[1]));
-      fl[it][2] = sc * (-(nx * d[4] - ny * d[3]) + alpha * (nz * ndE - d[2]));
-      fl[it][3] = sc * ((ny * d[2] - nz * d[1]) + alpha * (nx * ndH - d[3]));
-      fl[it][4] = sc * ((nz * d[0] - nx * d[2]) + alpha * (ny * ndH - d[4]));
-      fl[it][5] = sc * ((nx * d[1] - ny * d[0]) + alpha * (nz * ndH - d[5]));
+      fl[it][0] = scE * (-(ny * d[5] - nz * d[4]) + aE * (nx * ndE - d[0]));
+      fl[it][1] = scE * (-(nz * d[3] - nx * d[5]) + aE * (ny * ndE - d[1]));
+      fl[it][2] = scE * (-(nx * d[4] - ny * d[3]) + aE * (nz * ndE - d[2]));
+      fl[it][3] = scH * ((ny * d[2] - nz * d[1]) + aH * (nx * ndH - d[3]));
+      fl[it][4] = scH * ((nz * d[0] - nx * d[2]) + aH * (ny * ndH - d[4]));
+      fl[it][5] = scH * ((nx * d[1] - ny * d[0]) + aH * (nz * ndH - d[5]));
     }
   };
   // part -1: all fluxes, rows c NF + m; part 0 / 1 (split lift): the flux
@@ -801,7 +845,10 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   constexpr int kAheadRegs = sizeof(T) == 8 ? 112 : 40;  // VGPRs given to loads in flight
   constexpr int kAhead = RK ? (kItems * 8 <= kAheadRegs ? kItems : kAheadRegs / 8) : 0;
   VT rv[RK ? kItems : 1], uv[RK ? kItems : 1];
-  const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.res, RK ? 6u * uint32_t(fs) * sz : 0u);
+  // The first stage (rk_a = 0) reads no residual: an empty resource makes the
+  // residual loads return zero without touching memory, so whatever res holds
+  // on entry (NaN included) never enters the update.
+  const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.res, (RK && a.rk_a != 0.0) ? 6u * uint32_t(fs) * sz : 0u);
   auto vload = [&](__amdgpu_buffer_rsrc_t r, uint32_t vo) {
     return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, 0, 0));
   };
@@ -914,6 +961,15 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   out(std::false_type{});
 }
 
+// Minimum waves per SIMD the register allocation must allow (1: no
+// constraint).  Set where the unconstrained allocation lands one or two
+// registers past the 168 that three waves per SIMD allow (512 / 3, in
+// granules of 8), which the allocator then meets without spilling.
+template <int N, typename T, int MIX>
+constexpr int min_waves_per_simd() {
+  return (sizeof(T) == 4 && ((MIX == 0 && N == 6) || (MIX == 2 && N == 4))) ? 3 : 1;
+}
+
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous range of the
 // n tiles (launch 8 * ceil(n / 8) workgroups; the surplus returns).
 __device__ inline int64_t xcd_tile(int64_t n) {
@@ -921,11 +977,12 @@ __device__ inline int64_t xcd_tile(int64_t n) {
   return int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <int N, typename T, bool RK, int MIX>
-__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>())) void rhs_mfma_kernel(RhsArgs a) {
+template <int N, typename T, bool RK, int MIX, bool MAT = false>
+__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>()), (min_waves_per_simd<N, T, MIX>())) void rhs_mfma_kernel(
+    RhsArgs a) {
   const int64_t tile = xcd_tile((a.K + 15) / 16);
   if (tile >= (a.K + 15) / 16) return;
-  rhs_mfma_tile<N, T, RK, MIX>(a, tile);
+  rhs_mfma_tile<N, T, RK, MIX, MAT>(a, tile);
 }
 
 // One Runge-Kutta stage for every problem of a batch that has order N: the
@@ -933,7 +990,8 @@ __global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>())) void rhs_mfma_k
 // pointers come from the descriptor table.  parity 0 reads u and writes the
 // second state buffer, parity 1 the reverse.
 template <int N, typename T, int MIX>
-__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>())) void rk_mfma_batch_kernel(BatchArgs b) {
+__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>()), (min_waves_per_simd<N, T, MIX>())) void rk_mfma_batch_kernel(
+    BatchArgs b) {
   const int64_t item = xcd_tile(b.n_items);
   if (item >= b.n_items) return;
   const int2 w = b.items[item];
@@ -945,6 +1003,7 @@ __global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>())) void rk_mfma_ba
   a.rhs = nullptr;
   a.geo = P.geo;
   a.conn = P.conn;
+  a.mat = nullptr;
   a.ops = nullptr;
   a.ops_frag = b.ops_frag;
   a.ops_frag16 = b.ops_frag16;
@@ -967,19 +1026,21 @@ hipError_t launch_rk_mfma_batch(const BatchArgs& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int N, typename T, int MIX = 0>
+template <int N, typename T, int MIX = 0, bool MAT = false>
 hipError_t launch_rhs_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false, MIX>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s, a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false, MIX, MAT>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s,
+                     a);
   return hipGetLastError();
 }
 
-template <int N, typename T, int MIX = 0>
+template <int N, typename T, int MIX = 0, bool MAT = false>
 hipError_t launch_rk_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true, MIX>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s, a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true, MIX, MAT>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s,
+                     a);
   return hipGetLastError();
 }
 

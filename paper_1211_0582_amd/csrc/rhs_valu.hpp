@@ -6,8 +6,9 @@
 //      field holds the tile's E*Np values contiguously);
 //   2. flux gather: one lane per (element, face node) reads the own trace
 //      from LDS and the neighbour trace from global memory through the
-//      neighbour-node table, evaluates the upwind flux, scales it by Fscale
-//      and stores it in LDS (the facial buffer of Section 3 never goes to HBM);
+//      neighbour-node table (a boundary face mirrors the own trace),
+//      evaluates the upwind flux, scales it by Fscale and stores it in LDS
+//      (the facial buffer of Section 3 never goes to HBM);
 //   3. local differentiation + lifting: one lane per (element, node) forms
 //      Dr, Ds, Dt of all six fields from the LDS tile (operator columns read
 //      coalesced from the transposed matrices), applies the element's
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(256) void rhs_valu_kernel(RhsArgs a) {
   const T* __restrict__ u = static_cast<const T*>(a.u);
   T* __restrict__ rhs = static_cast<T*>(a.rhs);
   const T* __restrict__ geo = static_cast<const T*>(a.geo);
+  const T* __restrict__ mat = static_cast<const T*>(a.mat);  // nullptr: eps = mu = 1
   const T* __restrict__ ops = static_cast<const T*>(a.ops);
   const T* __restrict__ DrT = ops;
   const T* __restrict__ DsT = ops + Np * Np;
@@ -90,25 +92,37 @@ __global__ __launch_bounds__(256) void rhs_valu_kernel(RhsArgs a) {
       dhx = hx - u[3 * fs + g];
       dhy = hy - u[4 * fs + g];
       dhz = hz - u[5 * fs + g];
-    } else {  // perfectly conducting wall: E+ = -E-, H+ = H-
-      dex = T(2) * ex;
-      dey = T(2) * ey;
-      dez = T(2) * ez;
-      dhx = dhy = dhz = T(0);
+    } else {  // boundary face: E+ = se E-, H+ = sh H-
+      T se, sh;
+      exterior_factors<T>(code, se, sh);
+      dex = ex - se * ex;
+      dey = ey - se * ey;
+      dez = ez - se * ez;
+      dhx = hx - sh * hx;
+      dhy = hy - sh * hy;
+      dhz = hz - sh * hz;
     }
     const T* gf = geo + k * kGeoStride + 9 + 4 * f;
     const T nx = gf[0], ny = gf[1], nz = gf[2];
-    const T sc = T(0.5) * gf[3];
+    // vacuum: s_E = s_H = Fscale / 2, a_E = a_H = alpha; material: the record
+    T scE = T(0.5) * gf[3], scH = scE, aE = alpha, aH = alpha;
+    if (mat) {
+      const T* mf = mat + k * kMatStride + 2 + 4 * f;
+      scE = mf[0];
+      scH = mf[1];
+      aE = mf[2];
+      aH = mf[3];
+    }
     const T ndE = nx * dex + ny * dey + nz * dez;
     const T ndH = nx * dhx + ny * dhy + nz * dhz;
-    // fE = 1/2 [ -n x dH + alpha (n (n.dE) - dE) ]
-    sf[0][w] = sc * (-(ny * dhz - nz * dhy) + alpha * (nx * ndE - dex));
-    sf[1][w] = sc * (-(nz * dhx - nx * dhz) + alpha * (ny * ndE - dey));
-    sf[2][w] = sc * (-(nx * dhy - ny * dhx) + alpha * (nz * ndE - dez));
-    // fH = 1/2 [ n x dE + alpha (n (n.dH) - dH) ]
-    sf[3][w] = sc * ((ny * dez - nz * dey) + alpha * (nx * ndH - dhx));
-    sf[4][w] = sc * ((nz * dex - nx * dez) + alpha * (ny * ndH - dhy));
-    sf[5][w] = sc * ((nx * dey - ny * dex) + alpha * (nz * ndH - dhz));
+    // fE = s_E [ -n x dH + a_E (n (n.dE) - dE) ]
+    sf[0][w] = scE * (-(ny * dhz - nz * dhy) + aE * (nx * ndE - dex));
+    sf[1][w] = scE * (-(nz * dhx - nx * dhz) + aE * (ny * ndE - dey));
+    sf[2][w] = scE * (-(nx * dhy - ny * dhx) + aE * (nz * ndE - dez));
+    // fH = s_H [ n x dE + a_H (n (n.dH) - dH) ]
+    sf[3][w] = scH * ((ny * dez - nz * dey) + aH * (nx * ndH - dhx));
+    sf[4][w] = scH * ((nz * dex - nx * dez) + aH * (ny * ndH - dhy));
+    sf[5][w] = scH * ((nx * dey - ny * dex) + aH * (nz * ndH - dhz));
   }
   __syncthreads();
 
@@ -148,6 +162,15 @@ __global__ __launch_bounds__(256) void rhs_valu_kernel(RhsArgs a) {
 #undef DX
 #undef DY
 #undef DZ
+    if (mat) {  // volume term divided by eps (E) or mu (H); the fluxes already are
+      const T ie = mat[k * kMatStride], im = mat[k * kMatStride + 1];
+      out[0] *= ie;
+      out[1] *= ie;
+      out[2] *= ie;
+      out[3] *= im;
+      out[4] *= im;
+      out[5] *= im;
+    }
     const T* fe = &sf[0][e * NF];
 #pragma unroll 4
     for (int m = 0; m < NF; ++m) {

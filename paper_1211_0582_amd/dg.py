@@ -33,10 +33,15 @@ class DgError(RuntimeError):
         self.status = status
 
 
+DG_BC_CONDUCTING, DG_BC_MAGNETIC, DG_BC_ABSORBING = 0, 1, 2
+
+
 class MeshDesc(C.Structure):
     _fields_ = [("N", C.c_int32), ("precision", C.c_int32), ("alpha", C.c_double),
                 ("Nv", C.c_int64), ("VX", C.POINTER(C.c_double)),
-                ("K", C.c_int64), ("EToV", C.POINTER(C.c_int32))]
+                ("K", C.c_int64), ("EToV", C.POINTER(C.c_int32)),
+                ("face_bc", C.POINTER(C.c_int8)), ("eps", C.POINTER(C.c_double)),
+                ("mu", C.POINTER(C.c_double)), ("device", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -75,7 +80,7 @@ def _load():
         "dg_destroy_batch": (None, [P]),
         "dg_host_ref_nodes": (C.c_int, [C.c_int32, P, P, P]),
         "dg_host_ref_operators": (C.c_int, [C.c_int32, P, P, P, P, P, P]),
-        "dg_host_mesh": (C.c_int, [C.c_int32, C.c_int64, P, C.c_int64, P, P, P, P, P, P, P]),
+        "dg_host_mesh": (C.c_int, [C.c_int32, C.c_int64, P, C.c_int64, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -137,30 +142,63 @@ def dg_host_ref_operators(N):
     return dict(Dr=Dr, Ds=Ds, Dt=Dt, LIFT=LIFT, Fmask=Fmask, Mf=Mf)
 
 
-def dg_host_mesh(N, VX, EToV):
+def _face_bc(face_bc, K):
+    if face_bc is None:
+        return None
+    face_bc = np.ascontiguousarray(face_bc, dtype=np.int8)
+    if face_bc.shape != (K, 4):
+        raise ValueError(f"face_bc must have shape ({K}, 4)")
+    return face_bc
+
+
+def _per_element(v, K, name):
+    if v is None:
+        return None
+    v = np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (K,)))
+    return v
+
+
+def _cptr(a, ctype):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ctype))
+
+
+def dg_host_mesh(N, VX, EToV, face_bc=None):
     VX = np.ascontiguousarray(VX, dtype=np.float64)
     EToV = np.ascontiguousarray(EToV, dtype=np.int32)
     K = EToV.shape[0]
     Nfp = n_fp(N)
+    bc = _face_bc(face_bc, K)
     out = dict(metric=np.zeros((K, 9)), J=np.zeros(K), face=np.zeros((K, 4, 4)), sJ=np.zeros((K, 4)),
                vmapP=np.zeros((K, 4, Nfp), dtype=np.int64), conn=np.zeros((K, 4), dtype=np.int32))
-    _check(lib.dg_host_mesh(N, VX.shape[0], _ptr(VX), K, _ptr(EToV), _ptr(out["metric"]), _ptr(out["J"]),
-                            _ptr(out["face"]), _ptr(out["sJ"]), _ptr(out["vmapP"]), _ptr(out["conn"])))
+    _check(lib.dg_host_mesh(N, VX.shape[0], _ptr(VX), K, _ptr(EToV), None if bc is None else _ptr(bc),
+                            _ptr(out["metric"]), _ptr(out["J"]), _ptr(out["face"]), _ptr(out["sJ"]),
+                            _ptr(out["vmapP"]), _ptr(out["conn"])))
     return out
 
 
 # ---------------------------------------------------------------------------
 # Device calls
 # ---------------------------------------------------------------------------
-def dg_setup_mesh(N, VX, EToV, precision=DG_FP64, alpha=1.0):
+def mesh_desc(N, VX, EToV, precision=DG_FP64, alpha=1.0, face_bc=None, eps=None, mu=None, device=-1):
+    """(MeshDesc, keep-alive list of the host arrays it points into)."""
     VX = np.ascontiguousarray(VX, dtype=np.float64)
     EToV = np.ascontiguousarray(EToV, dtype=np.int32)
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
-    d = MeshDesc(N, precision, alpha, VX.shape[0], VX.ctypes.data_as(C.POINTER(C.c_double)),
-                 EToV.shape[0], EToV.ctypes.data_as(C.POINTER(C.c_int32)))
+    K = EToV.shape[0]
+    bc = _face_bc(face_bc, K)
+    ep = _per_element(eps, K, "eps")
+    mu_ = _per_element(mu, K, "mu")
+    d = MeshDesc(N, precision, alpha, VX.shape[0], _cptr(VX, C.c_double), K, _cptr(EToV, C.c_int32),
+                 _cptr(bc, C.c_int8), _cptr(ep, C.c_double), _cptr(mu_, C.c_double), int(device))
+    return d, [VX, EToV, bc, ep, mu_]
+
+
+def dg_setup_mesh(N, VX, EToV, precision=DG_FP64, alpha=1.0, face_bc=None, eps=None, mu=None, device=-1):
+    d, keep = mesh_desc(N, VX, EToV, precision, alpha, face_bc, eps, mu, device)
     h = C.c_void_p()
     _check(lib.dg_setup_mesh(C.byref(d), C.byref(h)))
+    del keep
     return h
 
 
@@ -235,9 +273,13 @@ def dg_set_variant(p, v):
 class Problem:
     """Owns a dg_problem handle; allocates state arrays as torch tensors."""
 
-    def __init__(self, N, VX, EToV, precision="fp64", alpha=1.0, tuned=False):
-        """tuned: apply the variant the autotuner cache holds for (N, precision)."""
-        self.handle = dg_setup_mesh(N, VX, EToV, precision, alpha)
+    def __init__(self, N, VX, EToV, precision="fp64", alpha=1.0, tuned=False, face_bc=None, eps=None, mu=None,
+                 device=-1):
+        """tuned: apply the variant the autotuner cache holds for (N, precision).
+        face_bc: (K, 4) boundary condition codes (DG_BC_*), eps / mu: per-element
+        material (scalar or (K,)), device: HIP device ordinal (-1: current)."""
+        self.handle = None
+        self.handle = dg_setup_mesh(N, VX, EToV, precision, alpha, face_bc, eps, mu, device)
         self.info = dg_info_get(self.handle)
         if tuned:
             from . import autotune
@@ -328,17 +370,17 @@ class Batch:
     """n independent problems stepped together (dg_setup_batch)."""
 
     def __init__(self, meshes, precision="fp32", alpha=1.0):
-        """meshes: list of (N, VX, EToV)."""
+        """meshes: list of (N, VX, EToV) or (N, VX, EToV, face_bc)."""
+        self.handle = None
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         keep = []
         descs = (MeshDesc * len(meshes))()
-        for i, (N, VX, EToV) in enumerate(meshes):
-            VX = np.ascontiguousarray(VX, dtype=np.float64)
-            EToV = np.ascontiguousarray(EToV, dtype=np.int32)
-            keep += [VX, EToV]
-            descs[i] = MeshDesc(N, precision, alpha, VX.shape[0], VX.ctypes.data_as(C.POINTER(C.c_double)),
-                                EToV.shape[0], EToV.ctypes.data_as(C.POINTER(C.c_int32)))
+        for i, mesh in enumerate(meshes):
+            N, VX, EToV = mesh[:3]
+            face_bc = mesh[3] if len(mesh) > 3 else None
+            descs[i], k = mesh_desc(N, VX, EToV, precision, alpha, face_bc)
+            keep += k
         h = C.c_void_p()
         _check(lib.dg_setup_batch(len(meshes), descs, C.byref(h)))
         self.handle = h

@@ -116,3 +116,45 @@ def test_setup_rejects_state_arrays_beyond_buffer_offsets():
     with pytest.raises(dg.DgError) as e:
         dg.dg_setup_mesh(9, VX, EToV, precision=dg.DG_FP64)
     assert e.value.status == dg.DG_EUNSUPPORTED and "2 GiB" in str(e.value)
+
+
+@pytest.mark.parametrize("N,k,seed", [(2, 2, 3), (4, 1, 7)])
+def test_boundary_codes_in_connectivity_match_oracle(N, k, seed):
+    """Boundary faces carry -1 - b for condition code b; interior faces keep
+    the neighbour word whatever face_bc says there (it is ignored)."""
+    VX, EToV = I.kuhn_cube(k, 0.1, seed)
+    K = EToV.shape[0]
+    bc = I.random_face_bc(K, seed + 11)
+    h = dg.dg_host_mesh(N, VX, EToV, bc)
+    m = Me.Mesh(N, VX, EToV, face_bc=bc)
+    bnd = m.EToE < 0
+    assert np.array_equal(h["conn"][bnd], -1 - m.bc[bnd])
+    plain = dg.dg_host_mesh(N, VX, EToV)
+    assert np.array_equal(h["conn"][~bnd], plain["conn"][~bnd])
+    assert np.all(plain["conn"][bnd] == -1)
+
+
+def test_descriptor_validation_without_a_gpu():
+    VX, EToV = I.kuhn_cube(1, 0.0, 0)
+    K = EToV.shape[0]
+    bad = np.zeros((K, 4), dtype=np.int8)
+    bad[0, :] = 3                      # element 0 has boundary faces on the unit cube's k = 1 mesh
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_host_mesh(2, VX, EToV, bad)
+    assert e.value.status == dg.DG_EINVAL and "condition code" in str(e.value)
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(2, VX, EToV, face_bc=bad)
+    assert e.value.status == dg.DG_EINVAL
+    for eps in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(dg.DgError) as e:
+            dg.dg_setup_mesh(2, VX, EToV, eps=eps)
+        assert e.value.status == dg.DG_EINVAL
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(2, VX, EToV, precision="f16x3", mu=2.0)
+    assert e.value.status == dg.DG_EUNSUPPORTED
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(2, VX, EToV, device=-2)
+    assert e.value.status == dg.DG_EINVAL
+    with pytest.raises(dg.DgError) as e:
+        dg.dg_setup_mesh(2, VX, EToV, device=4096)
+    assert e.value.status == dg.DG_EINVAL
