@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the DG Maxwell hot path on one MI355X.
 
-Workload (default): the 24^3 x 6 jittered Kuhn cube (K = 82,944 tetrahedra),
-order N = 4 (Np = 35), perfectly conducting walls, upwind flux, fields = the
-(1,1,0) cavity mode plus seeded N(0, 1e-3) noise.  One "step" is one LSERK
-time step: five right-hand-side evaluations, each fused with its stage
-update, over the whole mesh; the K timed steps are one dg_rk_step call.
+Workload (default, the largest single-GPU configuration): the 48^3 x 6
+jittered Kuhn cube (K = 663,552 tetrahedra), order N = 5 (Np = 56), FP32
+state, perfectly conducting walls, upwind flux, fields = the (1,1,0) cavity
+mode plus seeded N(0, 1e-3) noise.  One "step" is one LSERK time step: five
+right-hand-side evaluations, each fused with its stage update, over the whole
+mesh; the K timed steps are one dg_rk_step call.
 
 Metric: GDOF/s per RHS evaluation = 5 * 6 * K * Np * steps / time / 1e9,
 inputs resident in HBM, timed with HIP events on the stream the library
 launches on.  The "roofline" object describes the dominant kernel, the fused
 stage (right-hand side + update), from its algorithmic flop and byte counts
 and its average launch time over the timed region (time / (5 steps));
-"rhs_only" gives the same for the plain right-hand side timed by dg_time_rhs.
-"cpu_baseline" times the FP64 CPU oracle on a bounded sample.
+"rhs_only" gives the same for the plain right-hand side.  The same line
+carries the split 16-bit precisions on that mesh, the 24^3 x 6, N = 4 mesh in
+FP64 and FP32, and the 64-problem batch (graph replay vs one launch per
+problem).  "cpu_baseline" times the FP64 CPU oracle on a bounded sample of
+the same recipe.
 """
 from __future__ import annotations
 
@@ -87,12 +91,22 @@ def time_rhs(torch, p, du, out, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def cpu_baseline(VX, EToV, N, budget_s=20.0):
-    """FP64 oracle RHS evaluations of the same workload on the host cores; the
-    oracle receives the same fields, evaluated at its own nodes."""
-    from threadpoolctl import threadpool_info
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(k, N, budget_s, max_evals):
+    """(GDOF/s, evaluations, mean seconds, K) of FP64 oracle RHS evaluations on
+    the jittered k^3 x 6 cube at order N with the benchmark's fields."""
     from oracle import maxwell as Mx
     from oracle import mesh as Me
+    VX, EToV = I.kuhn_cube(k, 0.1, 0)
     m = Me.Mesh(N, VX, EToV)
     u = I.cavity_mode(m.x, m.y, m.z) + I.field_noise((6, m.K, m.Np), 1e-3, 1)
     t0 = time.perf_counter()
@@ -100,13 +114,28 @@ def cpu_baseline(VX, EToV, N, budget_s=20.0):
     while True:
         Mx.rhs(m, u)
         n += 1
-        if time.perf_counter() - t0 > budget_s / 2 or n >= 5:
+        if time.perf_counter() - t0 > budget_s or n >= max_evals:
             break
     t = (time.perf_counter() - t0) / n
+    return 6 * m.K * m.Np / t / 1e9, n, t, m.K
+
+
+def cpu_baseline(k, N, k_single):
+    """The FP64 CPU oracle on a bounded sample of the benchmark's recipe (the
+    per-DOF work of one RHS does not depend on K): all BLAS threads on the
+    k^3 x 6 mesh, and one thread on the smaller k_single mesh."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    return {"value": 6 * m.K * m.Np / t / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} FP64 oracle RHS evaluations of the same K={m.K}, N={N} mesh and fields "
-                      f"(mean {t:.2f} s each); host has {os.cpu_count()} logical CPUs"}
+    v, n, t, K = _oracle_rate(k, N, 12.0, 4)
+    with threadpool_limits(1):
+        v1, n1, t1, K1 = _oracle_rate(k_single, N, 4.0, 3)
+    return {"value": v, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} FP64 oracle RHS evaluations on the {k}^3x6 cube (K={K}, N={N}, the same mesh recipe "
+                      f"and fields at 1/{(48 // k) ** 3 if 48 % k == 0 else 'n'} of the elements; mean {t:.2f} s "
+                      f"each) with {threads} BLAS threads; the oracle's elementwise NumPy work is single-threaded",
+            "single_thread": {"value": v1, "unit": "GDOF/s", "cores": 1,
+                              "sample": f"{n1} evaluations on the {k_single}^3x6 cube (K={K1}), mean {t1:.2f} s"},
+            "host": {"cpu_model": _cpu_model(), "logical_cpus": os.cpu_count()}}
 
 
 def roofline(prec, N, K, t_rhs, s, stage=False):
@@ -181,9 +210,10 @@ def bench_sweep(args, torch, dg):
     print(json.dumps(line), flush=True)
 
 
-def bench_batch(args, torch, dg):
+def batch_modes(torch, dg, steps, warmup):
     """64 independent cavity problems (k ~ U{4..20}, N ~ U{2..7}, FP32) stepped
-    together: graph-replayed grouped launches vs one launch per problem."""
+    together: graph-replayed grouped launches, the same launches issued
+    directly, and one launch per problem and stage."""
     draws = I.batch_draws()
     meshes, dofs = [], 0
     for k, N, seed in draws:
@@ -201,53 +231,137 @@ def bench_batch(args, torch, dg):
     stream = torch.cuda.current_stream()
     out = {}
     for mode in ("graph", "grouped", "per_problem"):
-        b.rk_step(us, ress, dts, args.warmup, mode, stream)
+        b.rk_step(us, ress, dts, warmup, mode, stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
-        b.rk_step(us, ress, dts, args.steps, mode, stream)
+        b.rk_step(us, ress, dts, steps, mode, stream)
         e1.record(stream)
         e1.synchronize()
         wall = time.perf_counter() - t0
         t = e0.elapsed_time(e1) / 1e3
-        out[mode] = {"ms_per_step": 1e3 * t / args.steps, "gdofs": 5 * dofs * args.steps / t / 1e9,
-                     "host_ms_per_step": 1e3 * wall / args.steps}
+        out[mode] = {"ms_per_step": 1e3 * t / steps, "gdofs": 5 * dofs * steps / t / 1e9,
+                     "host_ms_per_step": 1e3 * wall / steps}
     b.close()
+    return {"workload": "64 independent PEC-cavity problems, k ~ U{4..20} (K = 6k^3), N ~ U{2..7}, FP32, "
+                        "one LSERK step of all of them per step",
+            "problems": len(draws), "dofs": dofs, "orders": sorted({n for _, n, _ in draws}), "modes": out,
+            "speedup_graph_vs_per_problem": out["per_problem"]["ms_per_step"] / out["graph"]["ms_per_step"]}
+
+
+def bench_batch(args, torch, dg):
+    r = batch_modes(torch, dg, args.steps, args.warmup)
     line = {
         "metric": "GDOF/s per DG RHS eval (Maxwell tets) and % of HBM/MFMA roofline",
-        "value": out["graph"]["gdofs"], "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": out["graph"]["ms_per_step"], "higher_is_better": True,
+        "value": r["modes"]["graph"]["gdofs"], "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["modes"]["graph"]["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "64 independent PEC-cavity problems, k ~ U{4..20} (K = 6k^3), N ~ U{2..7}, "
-                               "one LSERK step of all of them per step",
-                   "problems": len(draws), "dofs": dofs, "orders": sorted({n for _, n, _ in draws})},
-        "modes": out,
-        "speedup_graph_vs_per_problem": out["per_problem"]["ms_per_step"] / out["graph"]["ms_per_step"],
+        "config": {"workload": r["workload"], "problems": r["problems"], "dofs": r["dofs"], "orders": r["orders"]},
+        "modes": r["modes"], "speedup_graph_vs_per_problem": r["speedup_graph_vs_per_problem"],
     }
     print(json.dumps(line), flush=True)
+
+
+MIX = {"fp64": 0, "fp32": 0, "bf16": 1, "bf16x2": 2, "bf16x3": 3, "f16": 4, "f16x2": 5, "f16x3": 6}
+
+
+def measure(torch, dg, profiling, k, N, prec, steps, warmup, rhs_reps, variant=None, traffic_file=None):
+    """One mesh and precision: the LSERK step over `steps` steps in one call
+    (value, fused-stage roofline) and the plain right-hand side."""
+    p, u, mesh = make_problem(dg, k, N, prec)
+    if variant:
+        p.set_variant(variant)
+    K, Np = p.info.K, p.info.Np
+    s = p.info.elem_bytes
+    du = p.pack(u)
+    del u
+    res = p.zeros_state()
+    out = p.zeros_state()
+    dt = 0.5 * p.info.dt_cfl1
+    stream = torch.cuda.current_stream()
+    t_rhs = time_rhs(torch, p, du, out, rhs_reps)
+    # Warm-up and timed region: one dg_rk_step call each.  The fused stages
+    # ping-pong between two state buffers, so a call of n steps (5 n stages)
+    # needs a state copy at the end only when n is odd.
+    p.rk_step(du, res, 0.0, dt, warmup, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    p.rk_step(du, res, 0.0, dt, steps, stream)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    t_total = e0.elapsed_time(e1) / 1e3
+    t_stage = t_total / (5 * steps)   # average fused-stage launch in the timed region
+    dofs = 6 * K * Np
+    tname = "double" if prec == "fp64" else "float"
+    if p.variant == "mfma":
+        kname = f"void dgd::rhs_mfma_kernel<{N}, {tname}, true, {MIX[prec]}, false>(dgd::RhsArgs)"
+        kname_rhs = f"void dgd::rhs_mfma_kernel<{N}, {tname}, false, {MIX[prec]}, false>(dgd::RhsArgs)"
+    else:
+        kname = kname_rhs = f"void dgd::rhs_valu_kernel<{N}, {tname}>(dgd::RhsArgs)"
+    traffic_file = traffic_file or os.path.join(ROOT, "profiles", f"rhs_traffic_k{k}_n{N}.txt")
+    traffic = profiling.read_traffic(traffic_file, kname)
+    bound, achieved, peak, unit = roofline(prec, N, K, t_stage, s, stage=True)
+    if prec in ("fp64", "fp32") and p.variant != "mfma":
+        bound = "alu"
+    rb, ra, rp, ru = roofline(prec, N, K, t_rhs, s)
+    r = {
+        "value": 5 * dofs * steps / t_total / 1e9,
+        "ms_per_step": 1e3 * t_total / steps,
+        "stage_us": 1e6 * t_stage,
+        "rhs_us": 1e6 * t_rhs,
+        "rhs_gdofs": dofs / t_rhs / 1e9,
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak,
+                     "unit": unit, "frac": achieved / peak, "traffic": traffic,
+                     "kernel": kname,
+                     "launch_us": 1e6 * t_stage,
+                     "algorithmic_flops_per_launch": flops_per_element(N, True) * K,
+                     "algorithmic_bytes_per_launch": bytes_per_element(N, s, True) * K,
+                     "hbm_GBs_algorithmic": bytes_per_element(N, s, True) * K / t_stage / 1e9},
+        "rhs_only": {"kernel": kname_rhs, "launch_us": 1e6 * t_rhs, "bound": rb, "achieved": ra,
+                     "peak": rp, "unit": ru, "frac": ra / rp,
+                     "traffic": profiling.read_traffic(traffic_file, kname_rhs),
+                     "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K},
+        "K": K, "Np": Np, "variant": p.variant,
+    }
+    p.close()
+    del du, res, out
+    return r
+
+
+def _summary(r):
+    return {kk: r[kk] for kk in ("value", "ms_per_step", "stage_us", "rhs_us", "rhs_gdofs", "roofline", "rhs_only",
+                                 "variant", "K", "Np")}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--k", type=int, default=24, help="cube resolution (K = 6 k^3)")
-    ap.add_argument("--order", type=int, default=4)
-    ap.add_argument("--precision", default="fp64",
-                    choices=["fp64", "fp32", "bf16x3", "f16x3", "bf16x2", "f16x2", "bf16", "f16"])
-    ap.add_argument("--also", default="fp32,f16x3,bf16x3",
-                    help="other precisions measured in the same run (comma separated, may be empty)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="large", choices=["large", "single", "batch", "sweep"],
+                    help="large (default): 48^3 x 6 tets (K = 663,552), N = 5, FP32 headline plus the split "
+                         "precisions, the 24^3 x 6 N = 4 mesh and the 64-problem batch as extra keys; "
+                         "single: one mesh (--k, --order, --precision); batch: 64 independent problems; "
+                         "sweep: orders 1..9 at about 1e7 nodal values per field")
+    ap.add_argument("--k", type=int, default=None, help="cube resolution (K = 6 k^3); default 48 (large), 24 (single)")
+    ap.add_argument("--order", type=int, default=None, help="default 5 (large), 4 (single)")
+    ap.add_argument("--precision", default=None,
+                    choices=["fp64", "fp32", "bf16x3", "f16x3", "bf16x2", "f16x2", "bf16", "f16"],
+                    help="default fp32 (large), fp64 (single)")
+    ap.add_argument("--also", default=None,
+                    help="other precisions on the same mesh (comma separated, may be empty); "
+                         "default f16x3,bf16x3 (large), fp32,f16x3,bf16x3 (single)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="large workload: skip the 24^3 x 6 mesh and the batch")
     ap.add_argument("--rhs-reps", type=int, default=50)
     ap.add_argument("--variant", default=None, help="kernel variant (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one torch copy of 256 MiB (scale for the HBM traffic counters)")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "sweep", "large"],
-                    help="single: one mesh (default); batch: 64 independent problems stepped together; "
-                         "sweep: orders 1..9 at about 1e7 nodal values per field; "
-                         "large: 48^3 x 6 tets (K = 663,552), N = 5, FP32 and split precisions")
     ap.add_argument("--sweep-precisions", default="fp64,fp32,f16x3,bf16x3")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8,9")
     ap.add_argument("--traffic-file", default=None,
@@ -268,84 +382,25 @@ def main():
         return bench_batch(args, torch, dg)
     if args.workload == "sweep":
         return bench_sweep(args, torch, dg)
-    if args.workload == "large":
-        args.k, args.order = 48, 5
-        if args.precision == "fp64":
-            args.precision = "fp32"
-            args.also = "f16x3,bf16x3"
-        args.no_cpu_baseline = True
-    N, k = args.order, args.k
+    large = args.workload == "large"
+    k = args.k or (48 if large else 24)
+    N = args.order or (5 if large else 4)
+    prec = args.precision or ("fp32" if large else "fp64")
+    also = args.also if args.also is not None else ("f16x3,bf16x3" if large else "fp32,f16x3,bf16x3")
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    traffic_file = args.traffic_file or os.path.join(ROOT, "profiles", f"rhs_traffic_k{k}_n{N}.txt")
+    others = [x for x in also.split(",") if x and x != prec]
     results = {}
-    others = [x for x in args.also.split(",") if x and x != args.precision]
-    for prec in [args.precision] + others:
-        p, u, mesh = make_problem(dg, k, N, prec)
-        if args.variant:
-            p.set_variant(args.variant)
-        K, Np = p.info.K, p.info.Np
-        s = p.info.elem_bytes
-        du = p.pack(u)
-        res = p.zeros_state()
-        out = p.zeros_state()
-        dt = 0.5 * p.info.dt_cfl1
-        stream = torch.cuda.current_stream()
-        t_rhs = time_rhs(torch, p, du, out, args.rhs_reps)
-        # Warm-up and timed region: one dg_rk_step call each.  The fused
-        # stages ping-pong between two state buffers, so a call of n steps
-        # (5 n stages) needs a state copy at the end only when n is odd.
-        p.rk_step(du, res, 0.0, dt, args.warmup, stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        p.rk_step(du, res, 0.0, dt, args.steps, stream)
-        e1.record(stream)
-        e1.synchronize()
-        torch.cuda.synchronize()
-        t_total = e0.elapsed_time(e1) / 1e3
-        t_stage = t_total / (5 * args.steps)   # average fused-stage launch in the timed region
-        dofs = 6 * K * Np
-        tname = "double" if prec == "fp64" else "float"
-        mix = {"fp64": 0, "fp32": 0, "bf16": 1, "bf16x2": 2, "bf16x3": 3, "f16": 4, "f16x2": 5, "f16x3": 6}[prec]
-        if p.variant == "mfma":
-            kname = f"void dgd::rhs_mfma_kernel<{N}, {tname}, true, {mix}>(dgd::RhsArgs)"
-            kname_rhs = f"void dgd::rhs_mfma_kernel<{N}, {tname}, false, {mix}>(dgd::RhsArgs)"
-        else:
-            kname = kname_rhs = f"void dgd::rhs_valu_kernel<{N}, {tname}>(dgd::RhsArgs)"
-        traffic = profiling.read_traffic(traffic_file, kname)
-        bound, achieved, peak, unit = roofline(prec, N, K, t_stage, s, stage=True)
-        if prec in ("fp64", "fp32") and p.variant != "mfma":
-            bound = "alu"
-        rb, ra, rp, ru = roofline(prec, N, K, t_rhs, s)
-        results[prec] = {
-            "value": 5 * dofs * args.steps / t_total / 1e9,
-            "ms_per_step": 1e3 * t_total / args.steps,
-            "stage_us": 1e6 * t_stage,
-            "rhs_us": 1e6 * t_rhs,
-            "rhs_gdofs": dofs / t_rhs / 1e9,
-            "roofline": {"bound": bound, "achieved": achieved, "peak": peak,
-                         "unit": unit, "frac": achieved / peak, "traffic": traffic,
-                         "kernel": kname,
-                         "launch_us": 1e6 * t_stage,
-                         "algorithmic_flops_per_launch": flops_per_element(N, True) * K,
-                         "algorithmic_bytes_per_launch": bytes_per_element(N, s, True) * K,
-                         "hbm_GBs_algorithmic": bytes_per_element(N, s, True) * K / t_stage / 1e9},
-            "rhs_only": {"kernel": kname_rhs, "launch_us": 1e6 * t_rhs, "bound": rb, "achieved": ra,
-                         "peak": rp, "unit": ru, "frac": ra / rp,
-                         "traffic": profiling.read_traffic(traffic_file, kname_rhs),
-                         "algorithmic_bytes_per_launch": bytes_per_element(N, s) * K},
-            "K": K, "Np": Np, "variant": p.variant,
-        }
-        p.close()
-        del du, res, out
-
-    main_r = results[args.precision]
+    for pr in [prec] + others:
+        print(f"bench: k={k} N={N} {pr}", file=sys.stderr, flush=True)
+        results[pr] = measure(torch, dg, profiling, k, N, pr, args.steps, args.warmup, args.rhs_reps, args.variant,
+                              args.traffic_file)
+        torch.cuda.empty_cache()
+    main_r = results[prec]
     line = {
         "metric": "GDOF/s per DG RHS eval (Maxwell tets) and % of HBM/MFMA roofline",
         "value": main_r["value"],
@@ -357,22 +412,31 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32"}.get(args.precision, args.precision + "+f32acc"),
+        "dtype": {"fp64": "f64", "fp32": "f32"}.get(prec, prec + "+f32acc"),
         "data": "synthetic",
         "config": {"workload": f"jittered Kuhn cube {k}^3x6 tets (K={main_r['K']}), N={N} (Np={main_r['Np']}), "
-                               f"PEC cavity + noise, upwind, LSERK(5,4) step = 5 RHS + 5 updates",
-                   "K": main_r["K"], "N": N, "precision": args.precision, "variant": main_r["variant"]},
+                               f"{prec.upper()} state, PEC cavity + noise, upwind, "
+                               f"LSERK(5,4) step = 5 RHS + 5 updates",
+                   "K": main_r["K"], "N": N, "precision": prec, "variant": main_r["variant"]},
         "roofline": main_r["roofline"],
         "rhs_us": main_r["rhs_us"],
         "rhs_gdofs": main_r["rhs_gdofs"],
         "stage_us": main_r["stage_us"],
         "rhs_only": main_r["rhs_only"],
-        "other_precision": {o: {kk: results[o][kk] for kk in ("value", "ms_per_step", "stage_us", "rhs_us", "rhs_gdofs",
-                                                             "roofline", "rhs_only", "variant")} for o in others},
+        "other_precision": {o: _summary(results[o]) for o in others},
     }
+    if large and not args.no_extras:
+        small = {}
+        for pr in ("fp64", "fp32"):
+            print(f"bench: k=24 N=4 {pr}", file=sys.stderr, flush=True)
+            small[pr] = _summary(measure(torch, dg, profiling, 24, 4, pr, args.steps, args.warmup, args.rhs_reps))
+        line["mesh_24_n4"] = {"workload": "jittered Kuhn cube 24^3x6 tets (K=82944), N=4 (Np=35), "
+                                          "PEC cavity + noise, upwind, LSERK(5,4) step", "precisions": small}
+        print("bench: 64-problem batch", file=sys.stderr, flush=True)
+        line["batch"] = batch_modes(torch, dg, args.steps, args.warmup)
     if not args.no_cpu_baseline:
-        VX, EToV = I.kuhn_cube(k, 0.1, 0)
-        line["cpu_baseline"] = cpu_baseline(VX, EToV, N)
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(24 if k >= 24 else k, N, 12 if k >= 24 else max(2, k // 2))
     print(json.dumps(line), flush=True)
 
 

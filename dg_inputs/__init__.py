@@ -6,8 +6,9 @@ closed-form initial condition at coordinates that the caller supplies.  Both
 the FP64 CPU oracle and the HIP library receive exactly these arrays, so the
 two implementations never share a line of the method itself.
 
-Mesh recipe (the paper only speaks of "a large 3D Maxwell problem" on
-face-conforming tetrahedra, Sections 2 and 6): the unit cube [0,1]^3 cut into
+Mesh recipe (the paper leaves its Maxwell test meshes unspecified beyond
+being large, three-dimensional and made of face-conforming tetrahedra,
+Sections 2 and 5): the unit cube [0,1]^3 cut into
 k^3 hexahedra, each split into the six Kuhn tetrahedra that share the main
 diagonal, interior vertices jittered uniformly by up to 10% of h = 1/k.
 """

@@ -112,14 +112,14 @@ typedef struct {
                             device current at dg_setup_mesh                       */
 } dg_mesh_desc;
 
-/* Layout of device state arrays (u, rhs, res).  A state array holds the six
- * fields one after the other, field c starting at element offset
- * c * field_stride; inside a field, element k's Np nodal values are
- * contiguous at offset k * Np.  Entries between K*Np and field_stride are
- * padding: never read as data.  state_elems = 6 * field_stride scalars of
- * elem_bytes bytes each.  State arrays passed to the library must start on a
- * 16-byte boundary (hipMalloc gives 256); the kernels write them with 16-byte
- * stores. */
+/* Layout of device state arrays (u, rhs, res).  A state array holds the
+ * nfields fields (six for Maxwell) one after the other, field c starting at
+ * element offset c * field_stride; inside a field, element k's Np nodal
+ * values are contiguous at offset k * Np.  Entries between K*Np and
+ * field_stride are padding: never read as data.  state_elems =
+ * nfields * field_stride scalars of elem_bytes bytes each.  State arrays
+ * passed to the library must start on a 16-byte boundary (hipMalloc gives
+ * 256); the kernels write them with 16-byte stores. */
 typedef struct {
   int32_t N, Np, Nfp, precision;
   int64_t K;
@@ -130,7 +130,9 @@ typedef struct {
   double dt_cfl1;        /* 2 / ((N+1)^2 max Fscale): dt at CFL number 1          */
   double alpha;
   int64_t n_boundary_faces;
-  int32_t variant;       /* kernel variant in use (dg_variant_name)               */
+  int32_t variant;       /* kernel variant in use (dg_variant_name); a compiled
+                            system reports dg_variant_count()                     */
+  int32_t nfields;       /* fields per state array: 6, or a compiled system's M   */
 } dg_info;
 
 /* Builds the reference element (Section 2: nodal basis, D = M^-1 S, face mass
@@ -160,15 +162,32 @@ dg_status dg_info_get(dg_problem p, dg_info* info);
  * aligned), DG_EHIP (launch failure). */
 dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
 
-/* Kernel variants of the right-hand side, all computing the same operator:
- *   0 "valu": one workgroup per element tile on the vector ALUs;
- *   1 "mfma": one workgroup (2 or 4 waves) per tile of 16 elements, the
- *             contraction with [Dr|Ds|Dt|LIFT] on the matrix cores,
- *             Runge-Kutta stage fused into its epilogue.
- * dg_setup_mesh picks "mfma" where it is built for (N, precision), else
- * "valu".  dg_variant_name returns NULL outside 0 .. dg_variant_count()-1.
+/* Kernel variants of the right-hand side, all computing the same operator
+ * (the paper tunes its kernels by timing generated variants, Section 4):
+ *   0 "valu":            one workgroup per element tile on the vector ALUs
+ *                        (FP64 / FP32);
+ *   1 "mfma":            one workgroup (2 or 4 waves) per tile of 16
+ *                        elements, the contraction with [Dr|Ds|Dt|LIFT] on the
+ *                        matrix cores, Runge-Kutta stage fused into its
+ *                        epilogue, choices by built-in heuristics;
+ *   2 "mfma_waves":      the other number of waves per tile (2 <-> 4);
+ *   3 "mfma_prefetch":   the other operator-fragment prefetch depth;
+ *   4 "mfma_occupancy":  registers allocated for the occupancy the tile's LDS
+ *                        allows;
+ *   5 "mfma_interleave": flux work interleaved with the volume contraction
+ *                        or not, the other way round (FP64 / FP32);
+ *   6 "mfma_lift":       the lift in two halves or not, the other way round
+ *                        (FP64 / FP32);
+ *   7 "mfma_tail":       the last row block on the 4-row matrix-core form or
+ *                        not, the other way round (FP64 / FP32, where that
+ *                        block holds at most 4 nodes).
+ * Variants 2..7 exist where they give a different kernel (FP64, FP32 and the
+ * x3 split forms, vacuum flux); batches use "mfma".  dg_setup_mesh picks
+ * "mfma" where it is built for (N, precision), else "valu".
+ * dg_variant_name returns NULL outside 0 .. dg_variant_count()-1.
  * dg_set_variant: DG_EINVAL (null p, v out of range), DG_EUNSUPPORTED (not
- * built for this order and precision; the problem keeps its variant). */
+ * built for this order, precision and flux form; the problem keeps its
+ * variant). */
 int32_t dg_variant_count(void);
 const char* dg_variant_name(int32_t v);
 dg_status dg_set_variant(dg_problem p, int32_t v);
@@ -198,6 +217,36 @@ dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, in
  * nsteps < 0, dt not finite). */
 dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
                      int32_t nsteps, void* stream);
+
+/* ---- Run-time compiled systems (Section 4, run-time code generation) -----
+ * A hyperbolic system other than the built-in Maxwell one, given as C++
+ * source that defines `struct System` (M fields; volume flux, numerical flux
+ * n.F - (n.F)* and boundary exterior states as __device__ templates; the
+ * contract is spelled out in the library's rtc_kernel.hpp and produced by the
+ * Python front end paper_1211_0582_amd/systems.py).  The library puts it in
+ * front of its matrix-core kernel template and compiles it with hipRTC for
+ * the problem's order, precision and device, so the system's zero flux
+ * entries, N, Np and Nfp are all compile-time constants of the kernel.
+ *
+ * dg_system_compile: compiles only (no device needed) for the architecture
+ * `arch` (e.g. "gfx950"); the compiler log goes to log[0 .. log_size-1]
+ * (NUL-terminated; may be NULL).  Errors: DG_EINVAL (null source or arch,
+ * nfields outside 1..12, source that does not compile), DG_EUNSUPPORTED
+ * (N outside 1..9, precision other than FP64/FP32).
+ *
+ * dg_setup_system: as dg_setup_mesh for the system: state arrays hold
+ * nfields fields (dg_info.nfields); face_bc codes are passed to
+ * System::exterior; eps and mu must be NULL (or all 1).  dg_rhs, dg_rk_step
+ * (right-hand side plus the update kernel), dg_energy
+ * (sum_k J_k u^T M u / 2 over all fields), dg_pack/dg_unpack ([nfields][K][Np]),
+ * dg_time_rhs and dg_destroy apply; batches and dg_set_variant do not.  The
+ * compiled module is cached for the process (per device, architecture,
+ * order, precision and source).  Errors: as dg_setup_mesh and
+ * dg_system_compile, DG_EHIP (module load). */
+dg_status dg_system_compile(const char* system_source, int32_t nfields, int32_t N, int32_t precision,
+                            const char* arch, char* log, int64_t log_size);
+dg_status dg_setup_system(const dg_mesh_desc* desc, const char* system_source, int32_t nfields,
+                          dg_problem* out);
 
 /* ---- Batches of independent problems -------------------------------------
  * A batch owns n problems (any mix of orders and sizes, one precision) and
@@ -234,6 +283,19 @@ dg_status dg_rk_step_batch(dg_batch b, void* const* u, void* const* res, const d
 
 /* Releases the batch and its problems; NULL is a no-op. */
 void dg_destroy_batch(dg_batch b);
+
+/* On-device diagnostics: the discrete energy of u - ref in the mass-matrix
+ * norm of Section 2 (M^k = J_k M on affine elements, Section 2.1), weighted
+ * by the material,
+ *   *dev_out = 1/2 sum_k J_k [ eps_k dE^T M dE + mu_k dH^T M dH ],
+ * dE = E - E_ref, dH = H - H_ref, accumulated in binary64 in a fixed order
+ * (bitwise reproducible).  ref NULL gives the energy of u, which the upwind
+ * flux never increases; with ref the interpolated exact solution,
+ * sqrt(2 *dev_out) is the L2 error.  u, ref: device state arrays of the
+ * problem; dev_out: device pointer to one double.  Asynchronous on stream;
+ * uses a partial-sum buffer owned by the problem, so calls on one problem
+ * must not overlap.  Errors: DG_EINVAL (null p, u or dev_out), DG_EHIP. */
+dg_status dg_energy(dg_problem p, const void* u, const void* ref, double* dev_out, void* stream);
 
 /* Host <-> device conversion between the canonical host layout
  * [6][K][Np] binary64 (host pointer) and a device state array (layout above,

@@ -1,8 +1,8 @@
 """Five-stage, fourth-order low-storage Runge-Kutta (Carpenter & Kennedy, 2N storage).  Test infrastructure only.
 
-The paper times its solver "including RK4 timestepping" without naming the
-scheme; the reading taken here is the 5-stage 2N-storage RK4 of Carpenter and
-Kennedy (1994):
+The paper's timings (Section 5) cover whole time steps with a fourth-order
+Runge-Kutta update but do not name the scheme; the reading taken here is the
+5-stage 2N-storage RK4 of Carpenter and Kennedy (1994):
     res <- A_s res + dt f(u, t + C_s dt);   u <- u + B_s res,   s = 1..5, A_1 = 0.
 
 Parity: pinned by tests/test_oracle_lserk.py -- the stage coefficients,

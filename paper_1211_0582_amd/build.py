@@ -2,8 +2,8 @@
 
 Usage: ``python -m paper_1211_0582_amd.build`` (or ``build()`` from Python).
 Host-only setup code is compiled with g++, everything that touches HIP with
-hipcc; the per-order kernel file is compiled once per order N = 1..9 so the
-objects build in parallel.
+hipcc; the kernel file is compiled once per order N = 1..9 and precision
+group so the objects build in parallel.
 """
 from __future__ import annotations
 
@@ -32,19 +32,36 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
 
 
+def _embed_rtc_source() -> str:
+    """C++ file holding the text of rtc_kernel.hpp (the kernel template that
+    run-time compiled systems are built from) as kRtcKernelSource."""
+    text = open(os.path.join(CSRC, "rtc_kernel.hpp"), encoding="utf-8").read()
+    if ")DGRTC\"" in text:
+        raise RuntimeError("rtc_kernel.hpp contains the raw-string delimiter")
+    out = os.path.join(BUILD, "rtc_source.cpp")
+    body = 'extern const char kRtcKernelSource[];\nconst char kRtcKernelSource[] = R"DGRTC(' + text + ')DGRTC";\n'
+    if not os.path.exists(out) or open(out, encoding="utf-8").read() != body:
+        with open(out, "w", encoding="utf-8") as f:
+            f.write(body)
+    return out
+
+
 def _jobs():
     jobs = []
     for name in ("host_refelem.cpp", "host_mesh.cpp"):
         src = os.path.join(CSRC, name)
         jobs.append(([CXX, *HOST_FLAGS, "-c", src, "-o", os.path.join(BUILD, name + ".o")], name))
-    for name in ("api.cpp", "batch.cpp", "lserk.hip"):
+    src = _embed_rtc_source()
+    jobs.append(([CXX, *HOST_FLAGS, "-c", src, "-o", os.path.join(BUILD, "rtc_source.o")], "rtc_source.cpp"))
+    for name in ("api.cpp", "batch.cpp", "rtc.cpp", "lserk.hip", "diag.hip"):
         src = os.path.join(CSRC, name)
         lang = ["-x", "hip"] if name.endswith(".cpp") else []
         jobs.append(([HIPCC, *HIP_FLAGS, *lang, "-c", src, "-o", os.path.join(BUILD, name + ".o")], name))
     for n in ORDERS:
-        src = os.path.join(CSRC, "rhs_inst.hip")
-        jobs.append(([HIPCC, *HIP_FLAGS, f"-DDG_ORDER={n}", "-c", src, "-o", os.path.join(BUILD, f"rhs_n{n}.o")],
-                     f"rhs_inst.hip N={n}"))
+        for g in (0, 1, 2):   # precision groups: FP64, FP32, split 16-bit
+            src = os.path.join(CSRC, "rhs_inst.hip")
+            jobs.append(([HIPCC, *HIP_FLAGS, f"-DDG_ORDER={n}", f"-DDG_GROUP={g}", "-c", src, "-o",
+                          os.path.join(BUILD, f"rhs_n{n}_g{g}.o")], f"rhs_inst.hip N={n} group={g}"))
     return jobs
 
 
@@ -71,7 +88,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         raise RuntimeError("compilation failed: " + ", ".join(b[0] for b in bad))
     objs = [w[0][-1] for w in work]
     tmp = LIB + ".tmp"
-    link = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    link = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lhiprtc"]
     p = subprocess.run(link, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stdout + p.stderr)

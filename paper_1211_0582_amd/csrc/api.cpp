@@ -111,6 +111,9 @@ void free_problem(dg_problem p) {
   hipFree(p->d_frag16);
   hipFree(p->d_scratch);
   hipFree(p->d_mat);
+  hipFree(p->d_mass);
+  hipFree(p->d_weight);
+  hipFree(p->d_partial);
   delete p;
 }
 
@@ -136,6 +139,25 @@ std::vector<double> material_records(const HostMesh& hm, const double* eps, cons
     }
   }
   return rec;
+}
+
+// Diagnostics data: M = (V V^T)^-1, J eps and J mu per element, partial sums.
+dg_status upload_diag(dg_problem p, const RefElement& re, const HostMesh& hm, const double* eps, const double* mu) {
+  Mat M;
+  if (!invert(matmul(re.V, transpose(re.V)), M)) return fail(DG_EUNSUPPORTED, "singular Vandermonde");
+  std::vector<double> w(size_t(hm.K) * 2);
+  for (int64_t k = 0; k < hm.K; ++k) {
+    w[2 * k] = hm.J[k] * (eps ? eps[k] : 1.0);
+    w[2 * k + 1] = hm.J[k] * (mu ? mu[k] : 1.0);
+  }
+  const int E = dgd::energy_tile(re.Np);
+  const int64_t blocks = (hm.K + E - 1) / E;
+  DG_HIP(hipMalloc(&p->d_mass, M.a.size() * sizeof(double)), "hipMalloc(mass matrix)");
+  DG_HIP(hipMalloc(&p->d_weight, w.size() * sizeof(double)), "hipMalloc(element weights)");
+  DG_HIP(hipMalloc(&p->d_partial, size_t(blocks) * sizeof(double)), "hipMalloc(partial sums)");
+  DG_HIP(hipMemcpy(p->d_mass, M.a.data(), M.a.size() * sizeof(double), hipMemcpyHostToDevice), "upload mass");
+  DG_HIP(hipMemcpy(p->d_weight, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice), "upload weights");
+  return DG_OK;
 }
 
 template <typename T>
@@ -268,8 +290,68 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   return a;
 }
 
+dg_status check_rk_args(dg_problem p, const void* u, const void* res, double dt, int32_t nsteps) {
+  if (!p || !u || !res) return fail(DG_EINVAL, "null argument");
+  if (u == res) return fail(DG_EINVAL, "u and res must not alias");
+  if (!aligned16(u) || !aligned16(res)) return fail(DG_EINVAL, "state arrays must be 16-byte aligned");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  return DG_OK;
+}
+
+hipError_t launch_rhs(dg_problem p, const dgd::RhsArgs& a, hipStream_t s) {
+  return p->rtc_fn ? launch_rtc(p, a, s) : p->ks.rhs(a, s);
+}
+
+dg_status rk_steps(dg_problem p, void* u, void* res, double dt, int32_t nsteps, void* buf, hipStream_t s) {
+  const size_t bytes = size_t(p->state_elems) * p->elem_bytes;
+  if (p->ks.rk && !p->rtc_fn) {
+    // Fused stages: each stage reads one state buffer and writes the other
+    // (neighbours still read the input during the stage), res in place.
+    dgd::RhsArgs ra = rhs_args(p, u, nullptr);
+    void* cur = u;
+    void* nxt = buf;
+    ra.res = res;
+    ra.rk_dt = dt;
+    // u and res read, res and the other state buffer written.
+    ra.stream_out = 3 * p->state_elems * p->elem_bytes > kLastLevelCacheBytes;
+    for (int32_t n = 0; n < nsteps; ++n)
+      for (int st = 0; st < 5; ++st) {
+        ra.u = cur;
+        ra.u_out = nxt;
+        ra.rk_a = kRkA[st];
+        ra.rk_b = kRkB[st];
+        hipError_t e = p->ks.rk(ra, s);
+        if (e != hipSuccess) return hip_fail(e, "fused stage kernel launch");
+        std::swap(cur, nxt);
+      }
+    if (cur != u) DG_HIP(hipMemcpyAsync(u, cur, bytes, hipMemcpyDeviceToDevice, s), "state copy");
+    return DG_OK;
+  }
+  const dgd::RhsArgs ra = rhs_args(p, u, buf);
+  for (int32_t n = 0; n < nsteps; ++n)
+    for (int st = 0; st < 5; ++st) {
+      hipError_t e = launch_rhs(p, ra, s);
+      if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
+      dgd::UpdateArgs ua;
+      ua.u = u;
+      ua.res = res;
+      ua.rhs = buf;
+      ua.n = p->K * p->Np;
+      ua.fs = p->fs;
+      ua.nfields = p->nfields;
+      ua.a = kRkA[st];
+      ua.b = kRkB[st];
+      ua.dt = dt;
+      e = dgd::launch_update(ua, p->precision, s);
+      if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+    }
+  return DG_OK;
+}
+
 namespace {
-const char* const kVariantNames[dgd::kVariantCount] = {"valu", "mfma"};
+const char* const kVariantNames[dgd::kVariantCount] = {
+    "valu", "mfma", "mfma_waves", "mfma_prefetch", "mfma_occupancy", "mfma_interleave", "mfma_lift", "mfma_tail"};
 }  // namespace
 
 extern "C" {
@@ -332,8 +414,9 @@ dg_status dg_host_mesh(int32_t N, int64_t Nv, const double* VX, int64_t K, const
   return DG_OK;
 }
 
-dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
-  clear_error();
+}  // extern "C"
+
+dg_status setup_problem_impl(const dg_mesh_desc* desc, int nfields, bool system, dg_problem* out) {
   if (!desc || !out) return fail(DG_EINVAL, "null argument");
   if (desc->precision < DG_FP64 || desc->precision > DG_F16X2) return fail(DG_EINVAL, "precision out of range");
   if (!std::isfinite(desc->alpha)) return fail(DG_EINVAL, "alpha must be finite");
@@ -352,6 +435,7 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
         }
   if (material && desc->precision != DG_FP64 && desc->precision != DG_FP32)
     return fail(DG_EUNSUPPORTED, "eps or mu other than 1 needs precision FP64 or FP32");
+  if (material && system) return fail(DG_EUNSUPPORTED, "a compiled system takes no eps or mu");
   HostMesh hm;
   dg_status st = build_mesh(desc->N, desc->Nv, desc->VX, desc->K, desc->EToV, desc->face_bc, hm);
   if (st != DG_OK) return st;
@@ -362,7 +446,7 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
     // offset 2^31 as the "reads zero" sentinel, so an array must stay below it.
     const int64_t eb = desc->precision == DG_FP64 ? 8 : 4;
     const int64_t fs = ((desc->K * re->Np + 256 / eb - 1) / (256 / eb)) * (256 / eb);
-    if (6 * fs * eb >= (int64_t(1) << 31))
+    if (nfields * fs * eb >= (int64_t(1) << 31))
       return fail(DG_EUNSUPPORTED, "state array of 2 GiB or more (K * Np too large for this precision)");
   }
 
@@ -382,7 +466,8 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   // Each field starts on a 256-byte boundary.
   const int64_t align = 256 / p->elem_bytes;
   p->fs = ((p->K * p->Np + align - 1) / align) * align;
-  p->state_elems = 6 * p->fs;
+  p->nfields = nfields;
+  p->state_elems = int64_t(nfields) * p->fs;
   p->n_boundary = hm.n_boundary;
   p->material = material;
   // dt ~ dx / N^2 (Section 3's time-step restriction): 2 / ((N+1)^2 max Fscale)
@@ -395,18 +480,24 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
       cmax = std::max(cmax, 1.0 / std::sqrt((desc->eps ? desc->eps[k] : 1.0) * (desc->mu ? desc->mu[k] : 1.0)));
   }
   p->dt_cfl1 = 2.0 / ((desc->N + 1.0) * (desc->N + 1.0) * hm.max_fscale * cmax);
-  // Default kernel: the matrix-core variant where it is built, else the vector one.
-  p->variant = dgd::kVariantMfma;
-  p->ks = dgd::kernels(desc->N, desc->precision, p->variant, material);
-  if (!p->ks.rhs) {
-    p->variant = dgd::kVariantValu;
+  // Default kernel: the matrix-core variant where it is built, else the vector
+  // one (a compiled system brings its own kernel).
+  if (system) {
+    p->variant = dgd::kVariantCount;  // "system"
+    p->tile = 16;
+  } else {
+    p->variant = dgd::kVariantMfma;
     p->ks = dgd::kernels(desc->N, desc->precision, p->variant, material);
+    if (!p->ks.rhs) {
+      p->variant = dgd::kVariantValu;
+      p->ks = dgd::kernels(desc->N, desc->precision, p->variant, material);
+    }
+    if (!p->ks.rhs) {
+      delete p;
+      return fail(DG_EUNSUPPORTED, "no kernel for this order and precision");
+    }
+    p->tile = p->ks.tile;
   }
-  if (!p->ks.rhs) {
-    delete p;
-    return fail(DG_EUNSUPPORTED, "no kernel for this order and precision");
-  }
-  p->tile = p->ks.tile;
   p->device = dev;
   p->verts.resize(size_t(p->K) * 12);
   for (int64_t k = 0; k < p->K; ++k)
@@ -414,6 +505,7 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
       for (int d = 0; d < 3; ++d) p->verts[size_t(k) * 12 + v * 3 + d] = desc->VX[3 * int64_t(desc->EToV[4 * k + v]) + d];
   const std::vector<double> mat = material ? material_records(hm, desc->eps, desc->mu, desc->alpha) : std::vector<double>();
   st = (p->precision == DG_FP64) ? upload<double>(p, *re, hm, mat) : upload<float>(p, *re, hm, mat);
+  if (st == DG_OK) st = upload_diag(p, *re, hm, desc->eps, desc->mu);
   if (st != DG_OK) {
     free_problem(p);
     return st;
@@ -421,6 +513,17 @@ dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
   *out = p;
   return DG_OK;
 }
+
+dg_status setup_problem(const dg_mesh_desc* desc, int nfields, bool system, dg_problem* out) {
+  return setup_problem_impl(desc, nfields, system, out);
+}
+
+extern "C" dg_status dg_setup_mesh(const dg_mesh_desc* desc, dg_problem* out) {
+  clear_error();
+  return setup_problem_impl(desc, 6, false, out);
+}
+
+extern "C" {
 
 dg_status dg_info_get(dg_problem p, dg_info* info) {
   clear_error();
@@ -438,6 +541,7 @@ dg_status dg_info_get(dg_problem p, dg_info* info) {
   info->alpha = p->alpha;
   info->n_boundary_faces = p->n_boundary;
   info->variant = p->variant;
+  info->nfields = p->nfields;
   return DG_OK;
 }
 
@@ -448,6 +552,7 @@ const char* dg_variant_name(int32_t v) { return (v >= 0 && v < dgd::kVariantCoun
 dg_status dg_set_variant(dg_problem p, int32_t v) {
   clear_error();
   if (!p) return fail(DG_EINVAL, "null problem");
+  if (p->rtc_fn) return fail(DG_EUNSUPPORTED, "a compiled system has exactly one kernel");
   if (v < 0 || v >= dgd::kVariantCount) return fail(DG_EINVAL, "variant out of range");
   dgd::KernelSet k = dgd::kernels(p->N, p->precision, v, p->material);
   if (!k.rhs) return fail(DG_EUNSUPPORTED, "variant not built for this order/precision");
@@ -462,10 +567,10 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream) {
   if (!p || !u || !rhs) return fail(DG_EINVAL, "null argument");
   if (u == rhs) return fail(DG_EINVAL, "u and rhs must not alias");
   if (!aligned16(u) || !aligned16(rhs)) return fail(DG_EINVAL, "state arrays must be 16-byte aligned");
-  if (!p->ks.rhs) return fail(DG_EUNSUPPORTED, "no kernel for this order/precision");
+  if (!p->ks.rhs && !p->rtc_fn) return fail(DG_EUNSUPPORTED, "no kernel for this order/precision");
   DeviceGuard guard(p->device);
   if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
-  hipError_t e = p->ks.rhs(rhs_args(p, u, rhs), static_cast<hipStream_t>(stream));
+  hipError_t e = launch_rhs(p, rhs_args(p, u, rhs), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
   return DG_OK;
 }
@@ -507,55 +612,21 @@ dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, in
 dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt, int32_t nsteps, void* stream) {
   clear_error();
   (void)t;
-  if (!p || !u || !res) return fail(DG_EINVAL, "null argument");
-  if (u == res) return fail(DG_EINVAL, "u and res must not alias");
-  if (!aligned16(u) || !aligned16(res)) return fail(DG_EINVAL, "state arrays must be 16-byte aligned");
-  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
-  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  dg_status st = check_rk_args(p, u, res, dt, nsteps);
+  if (st != DG_OK) return st;
   DeviceGuard guard(p->device);
   if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t bytes = size_t(p->state_elems) * p->elem_bytes;
-  if (p->ks.rk) {
-    // Fused stages: each stage reads one state buffer and writes the other
-    // (neighbours still read the input during the stage), res in place.
-    dgd::RhsArgs ra = rhs_args(p, u, nullptr);
-    void* cur = u;
-    void* nxt = p->d_scratch;
-    ra.res = res;
-    ra.rk_dt = dt;
-    // u and res read, res and the other state buffer written.
-    ra.stream_out = 3 * p->state_elems * p->elem_bytes > kLastLevelCacheBytes;
-    for (int32_t n = 0; n < nsteps; ++n)
-      for (int st = 0; st < 5; ++st) {
-        ra.u = cur;
-        ra.u_out = nxt;
-        ra.rk_a = kRkA[st];
-        ra.rk_b = kRkB[st];
-        hipError_t e = p->ks.rk(ra, s);
-        if (e != hipSuccess) return hip_fail(e, "fused stage kernel launch");
-        std::swap(cur, nxt);
-      }
-    if (cur != u) DG_HIP(hipMemcpyAsync(u, cur, bytes, hipMemcpyDeviceToDevice, s), "state copy");
-    return DG_OK;
-  }
-  const dgd::RhsArgs ra = rhs_args(p, u, p->d_scratch);
-  for (int32_t n = 0; n < nsteps; ++n)
-    for (int st = 0; st < 5; ++st) {
-      hipError_t e = p->ks.rhs(ra, s);
-      if (e != hipSuccess) return hip_fail(e, "rhs kernel launch");
-      dgd::UpdateArgs ua;
-      ua.u = u;
-      ua.res = res;
-      ua.rhs = p->d_scratch;
-      ua.n = p->K * p->Np;
-      ua.fs = p->fs;
-      ua.a = kRkA[st];
-      ua.b = kRkB[st];
-      ua.dt = dt;
-      e = dgd::launch_update(ua, p->precision, s);
-      if (e != hipSuccess) return hip_fail(e, "update kernel launch");
-    }
+  return rk_steps(p, u, res, dt, nsteps, p->d_scratch, static_cast<hipStream_t>(stream));
+}
+
+dg_status dg_energy(dg_problem p, const void* u, const void* ref, double* dev_out, void* stream) {
+  clear_error();
+  if (!p || !u || !dev_out) return fail(DG_EINVAL, "null argument");
+  DeviceGuard guard(p->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hipSetDevice");
+  hipError_t e = dgd::launch_energy(u, ref, p->d_mass, p->d_weight, p->K, p->fs, p->Np, p->nfields,
+                                    p->precision == DG_FP64, p->d_partial, dev_out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "energy kernel launch");
   return DG_OK;
 }
 
@@ -568,12 +639,12 @@ dg_status dg_pack(dg_problem p, const double* host_u, void* dev_u, void* stream)
   const int64_t n = p->K * p->Np;
   if (p->precision == DG_FP64) {
     std::vector<double> st(size_t(p->state_elems), 0.0);
-    for (int c = 0; c < 6; ++c) std::memcpy(&st[size_t(c * p->fs)], host_u + c * n, size_t(n) * sizeof(double));
+    for (int c = 0; c < p->nfields; ++c) std::memcpy(&st[size_t(c * p->fs)], host_u + c * n, size_t(n) * sizeof(double));
     DG_HIP(hipMemcpyAsync(dev_u, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s), "pack copy");
     DG_HIP(hipStreamSynchronize(s), "pack sync");
   } else {
     std::vector<float> st(size_t(p->state_elems), 0.0f);
-    for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < p->nfields; ++c)
       for (int64_t i = 0; i < n; ++i) st[size_t(c * p->fs + i)] = float(host_u[c * n + i]);
     DG_HIP(hipMemcpyAsync(dev_u, st.data(), st.size() * sizeof(float), hipMemcpyHostToDevice, s), "pack copy");
     DG_HIP(hipStreamSynchronize(s), "pack sync");
@@ -592,12 +663,12 @@ dg_status dg_unpack(dg_problem p, const void* dev_u, double* host_u, void* strea
     std::vector<double> st(size_t(p->state_elems));
     DG_HIP(hipMemcpyAsync(st.data(), dev_u, st.size() * sizeof(double), hipMemcpyDeviceToHost, s), "unpack copy");
     DG_HIP(hipStreamSynchronize(s), "unpack sync");
-    for (int c = 0; c < 6; ++c) std::memcpy(host_u + c * n, &st[size_t(c * p->fs)], size_t(n) * sizeof(double));
+    for (int c = 0; c < p->nfields; ++c) std::memcpy(host_u + c * n, &st[size_t(c * p->fs)], size_t(n) * sizeof(double));
   } else {
     std::vector<float> st(size_t(p->state_elems));
     DG_HIP(hipMemcpyAsync(st.data(), dev_u, st.size() * sizeof(float), hipMemcpyDeviceToHost, s), "unpack copy");
     DG_HIP(hipStreamSynchronize(s), "unpack sync");
-    for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < p->nfields; ++c)
       for (int64_t i = 0; i < n; ++i) host_u[c * n + i] = double(st[size_t(c * p->fs + i)]);
   }
   return DG_OK;

@@ -90,13 +90,15 @@ struct UpdateArgs {
   const void* rhs;
   int64_t n;              // K * Np scalars per field
   int64_t fs;
+  int nfields;
   double a, b, dt;
 };
 
 using RhsLauncher = hipError_t (*)(const RhsArgs&, hipStream_t);
 
-// Kernel variants of the right-hand side.
-enum Variant { kVariantValu = 0, kVariantMfma = 1, kVariantCount = 2 };
+// Kernel variants of the right-hand side: the vector-ALU kernel, then the
+// matrix-core kernel in each tuning configuration (kVariantMfma + kCfg*).
+enum Variant { kVariantValu = 0, kVariantMfma = 1, kVariantCount = 8 };
 
 struct KernelSet {
   RhsLauncher rhs = nullptr;  // writes rhs

@@ -115,19 +115,53 @@ struct MfmaShape {
   }
 };
 
+// Tuning configurations of the matrix-core kernels: the autotuner's search
+// space (the paper tunes its work decomposition by timing generated
+// variants, Section 4).  kCfgDefault takes the heuristics below; every other
+// configuration changes exactly one of them: the waves per tile, the
+// operator-fragment prefetch depth, the occupancy the register allocation
+// must allow, the flux interleave, the split lift, the 4-row tail block.
+enum : int {
+  kCfgDefault = 0,
+  kCfgWaves = 1,
+  kCfgPrefetch = 2,
+  kCfgOccupancy = 3,
+  kCfgInterleave = 4,
+  kCfgLift = 5,
+  kCfgTail = 6,
+  kCfgCount = 7
+};
+
 // Waves per tile: 2 (wave 0 the E equations, wave 1 the H equations, all row
 // blocks each) or 4 (the same two roles, each split over two waves by row
-// blocks).  Four halves the accumulators and operator-fragment traffic per
+// blocks; with an odd number of blocks the first wave of a role takes one
+// more).  Four halves the accumulators and operator-fragment traffic per
 // wave, which at high order is what bounds the waves per SIMD, at the price
 // of forming the volume operand twice (N = 7, FP32: 1 -> 2 waves per SIMD,
-// 42% -> 55% of peak).
-template <int N, typename T, int MIX>
+// 42% -> 55% of peak).  kCfgWaves takes the other choice (four waves need at
+// least two row blocks).
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int waves_per_tile() {
   constexpr int RB = MfmaShape<N>::RB;
   // The split forms pay for the duplicated operand split; measured on
   // MI355X four waves win from N = 5 for FP64/FP32 and from N = 6 for them.
   constexpr int min_rb = MIX == 0 ? 4 : 6;
-  return (RB >= min_rb && RB % 2 == 0) ? 4 : 2;
+  constexpr int d = RB >= min_rb ? 4 : 2;
+  if constexpr (CFG == kCfgWaves) return d == 4 ? 2 : (RB >= 2 ? 4 : 2);
+  return d;
+}
+
+// Row blocks of the first wave of a role (all of them with two waves per
+// tile, the larger half with four) and of the second.
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
+constexpr int row_blocks_first() {
+  constexpr int RB = MfmaShape<N>::RB;
+  return waves_per_tile<N, T, MIX, CFG>() == 2 ? RB : (RB + 1) / 2;
+}
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
+constexpr int row_blocks_second() {
+  return waves_per_tile<N, T, MIX, CFG>() == 2 ? MfmaShape<N>::RB
+                                               : MfmaShape<N>::RB - row_blocks_first<N, T, MIX, CFG>();
 }
 
 // Whether the last 16-row block, which holds at most 4 nodes (N = 1, 3, 4,
@@ -136,10 +170,13 @@ constexpr int waves_per_tile() {
 // four, to the wave of each role that owns the upper row blocks, which then
 // runs its own copy of the wave code -- in FP32 at N = 6 that copy would cost
 // a wave per SIMD (168 -> 184 registers), so there only FP64 uses it.
-template <int N, typename T, int MIX>
+// kCfgTail takes the other choice where the last block qualifies.
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr bool mfma_tail() {
   using S = MfmaShape<N>;
-  return MIX == 0 && S::Np - 16 * (S::RB - 1) <= 4 && (waves_per_tile<N, T, MIX>() == 2 || sizeof(T) == 8);
+  constexpr bool fits = MIX == 0 && S::Np - 16 * (S::RB - 1) <= 4;
+  constexpr bool d = fits && (waves_per_tile<N, T, MIX, CFG>() == 2 || sizeof(T) == 8);
+  return CFG == kCfgTail ? (fits && !d) : d;
 }
 
 template <int N, typename T>
@@ -148,11 +185,12 @@ constexpr size_t mfma_lds_bytes() {
 }
 
 // Whether the MFMA variant is built for (N, T): the LDS tile and the
-// accumulators (row blocks per wave x 3 x 4 scalars per lane) must fit.
-template <int N, typename T>
+// accumulators (row blocks per wave x 3 x 4 scalars per lane, at most 144
+// registers) must fit.
+template <int N, typename T, int MIX = 0, int CFG = kCfgDefault>
 constexpr bool mfma_supported() {
-  constexpr int RBW = MfmaShape<N>::RB * 2 / waves_per_tile<N, T, 0>();  // row blocks per wave
-  return mfma_lds_bytes<N, T>() <= 160 * 1024 && RBW * 3 * 4 * sizeof(T) / 4 <= 128;
+  constexpr int RBW = row_blocks_first<N, T, MIX, CFG>();
+  return mfma_lds_bytes<N, T>() <= 160 * 1024 && RBW * 3 * 4 * sizeof(T) / 4 <= 144;
 }
 
 // Raw buffer loads: a 128-bit resource (base, size) in SGPRs plus a 32-bit
@@ -213,7 +251,7 @@ struct FluxSchedule {
 // waits for the tile's readers and writes the fluxes over the field tile.
 // The wave produces row blocks rb0 .. rb0 + RBW - 1 of its three components
 // (all RB blocks with two waves per tile, half of them with four).
-template <int N, typename T, int H, bool IL, int NFI, int RBW, bool TW, typename Tile, typename Gather,
+template <int N, typename T, int H, bool IL, int NFI, int RBW, bool TW, bool PALT, typename Tile, typename Gather,
           typename FluxStep, typename FluxStore>
 __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a, Tile& t, const T (&mr)[9], int lane, int rb0,
                                  typename Mfma16<T>::acc (&acc)[RBW][3], Gather&& gather,
@@ -243,8 +281,10 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
 
   // Software pipeline: global loads are issued kPre depth steps before use
   // (one step when the accumulators already take most of the registers;
-  // more when the gathers sit in the load queue behind them).
-  constexpr int kPre = IL ? (RB >= 4 ? 2 : 4) : (RB >= 6 ? 1 : 2);
+  // more when the gathers sit in the load queue behind them).  PALT takes
+  // the alternative depth (1 <-> 2, 4 -> 2).
+  constexpr int kPreD = IL ? (RB >= 4 ? 2 : 4) : (RB >= 6 ? 1 : 2);
+  constexpr int kPre = PALT ? (kPreD == 2 ? 1 : 2) : kPreD;
   constexpr int NV = 3 * KSV;  // volume depth steps, ordered (ks, d)
   using FS = FluxSchedule<NV, NFI, kPre>;
   const uint32_t lane_off = uint32_t(lane + rb0 * KS * 64) * sz;
@@ -408,8 +448,8 @@ __device__ inline void split4(const float (&x)[4], typename Mfma16x16<H16>::v4& 
   }
 }
 
-template <int N, typename H16, int NPROD, int H, bool IL, int NFI, int RBW, typename Gather, typename FluxStep,
-          typename FluxStore>
+template <int N, typename H16, int NPROD, int H, bool IL, int NFI, int RBW, bool PALT, typename Gather,
+          typename FluxStep, typename FluxStore>
 __device__ __attribute__((always_inline)) inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane, int rb0,
                                   f32x4 (&acc)[RBW][3], Gather&& gather, FluxStep&& flux_step,
                                   FluxStore&& flux_store) {
@@ -426,8 +466,8 @@ __device__ __attribute__((always_inline)) inline void mixed_wave(const RhsArgs& 
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[ib][c] = f32x4{0, 0, 0, 0};
 
-  // A fragments (head, tail) prefetched kPre steps ahead.
-  constexpr int kPre = 2;
+  // A fragments (head, tail) prefetched kPre steps ahead (PALT: one step).
+  constexpr int kPre = PALT ? 1 : 2;
   using FS = FluxSchedule<SV, NFI, kPre>;
   auto frag_of = [&](int step, int ib, v4& hi, v4& lo) {
     const uint32_t off = uint32_t((((rb0 + ib) * ST + step) * 64 + lane) * 16);
@@ -540,19 +580,21 @@ __device__ __attribute__((always_inline)) inline void mixed_wave(const RhsArgs& 
 // SIMD and gains nothing: the FP32 matrix and vector pipes never co-issue
 // (SQ_VALU_MFMA_COEXEC_CYCLES reads 0), and the split forms are bound by the
 // vector ALU already.
-template <int N, typename T, int MIX>
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr bool flux_interleaved() {
   constexpr int iters = (16 * MfmaShape<N>::NF + 127) / 128;
-  return sizeof(T) == 8 && iters * 6 * sizeof(T) / 4 <= 72;
+  constexpr bool d = MIX == 0 && sizeof(T) == 8 && iters * 6 * sizeof(T) / 4 <= 72;
+  return CFG == kCfgInterleave ? (MIX == 0 && !d) : d;
 }
 
 // Whether the lift runs in two halves (see MfmaShape::tile): it trades two
 // barriers for a smaller flux region.  Used where the flux region sets the
 // LDS size and the registers allow one more workgroup per CU once it
 // shrinks: FP64 at N = 4 (3 -> 4 workgroups per CU).
-template <int N, typename T, int MIX>
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr bool lift_split() {
-  return MIX == 0 && sizeof(T) == 8 && N == 4;
+  constexpr bool d = MIX == 0 && sizeof(T) == 8 && N == 4;
+  return CFG == kCfgLift ? (MIX == 0 && !d) : d;
 }
 
 // Workgroup = two or four waves sharing one tile of 16 elements; wave role
@@ -564,16 +606,20 @@ constexpr bool lift_split() {
 // MAT: per-element eps and mu (material record, see kMatStride): the metric
 // of the volume operand is scaled by 1 / eps (E role) or 1 / mu (H role), and
 // the flux takes the record's per-face scales and upwind weights.
-template <int N, typename T, bool RK, int MIX, bool MAT = false>
+//
+// CFG: tuning configuration (kCfg*).
+template <int N, typename T, bool RK, int MIX, bool MAT = false, int CFG = kCfgDefault>
 __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArgs& a, int64_t tile) {
   using S = MfmaShape<N>;
   using M = Mfma16<T>;
   using acc_t = typename M::acc;
   constexpr int Np = S::Np, Nfp = S::Nfp, NF = S::NF, Np4 = S::Np4, RB = S::RB, TS = S::TS, TQ = S::TQ;
-  constexpr bool LIFT_HALF = lift_split<N, T, MIX>();
-  constexpr int WPT = waves_per_tile<N, T, MIX>();
+  constexpr bool LIFT_HALF = lift_split<N, T, MIX, CFG>();
+  constexpr int WPT = waves_per_tile<N, T, MIX, CFG>();
+  constexpr bool PALT = CFG == kCfgPrefetch;
   constexpr int NT = 64 * WPT;        // lanes per tile
-  constexpr int RBW = RB * 2 / WPT;   // row blocks per wave
+  constexpr int RBW = row_blocks_first<N, T, MIX, CFG>();    // row blocks of a role's first wave
+  constexpr int RBW1 = row_blocks_second<N, T, MIX, CFG>();  // and of its second (four waves per tile)
   __shared__ MfmaTile<N, T, LIFT_HALF, MAT> t;
   constexpr int FREC = MfmaTile<N, T, LIFT_HALF, MAT>::kFaceRec;
 
@@ -792,35 +838,55 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     }
   };
 
-  constexpr bool IL = flux_interleaved<N, T, MIX>();
+  constexpr bool IL = flux_interleaved<N, T, MIX, CFG>();
   static_assert(WPT == 2 || (!IL && !LIFT_HALF), "interleaved flux and split lift assume 128 lanes per tile");
   acc_t acc[RBW][3];
+  using B0 = std::integral_constant<int, RBW>;
+  using B1 = std::integral_constant<int, RBW1>;
+  // The waves of a role run one copy of the wave code when they own equal
+  // numbers of row blocks and no 4-row tail, else one copy each.
+  constexpr bool TAIL = mfma_tail<N, T, MIX, CFG>();
+  constexpr bool ONE_COPY = WPT == 2 || (!TAIL && RBW1 == RBW);
+  const int nb = (WPT == 2 || rh == 0) ? RBW : RBW1;  // row blocks of this wave
   if constexpr (MIX == 0) {
-    constexpr bool TAIL = mfma_tail<N, T, MIX>();
-    auto role = [&](auto tw) {
+    auto role = [&](auto tw, auto blocks) {
       constexpr bool TW = decltype(tw)::value;
+      constexpr int NB = decltype(blocks)::value;
+      auto& ac = reinterpret_cast<acc_t(&)[NB][3]>(acc);
       if (h == 0)
-        mfma_wave<N, T, 0, IL, kFluxIters, RBW, TW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
+        mfma_wave<N, T, 0, IL, kFluxIters, NB, TW, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step, flux_store);
       else
-        mfma_wave<N, T, 1, IL, kFluxIters, RBW, TW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
+        mfma_wave<N, T, 1, IL, kFluxIters, NB, TW, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step, flux_store);
     };
-    if constexpr (!TAIL) {
-      role(std::false_type{});
-    } else if constexpr (WPT == 2) {
-      role(std::true_type{});
+    if constexpr (ONE_COPY) {
+      role(std::integral_constant<bool, TAIL>{}, B0{});
     } else {
       if (rh == 1)
-        role(std::true_type{});
+        role(std::integral_constant<bool, TAIL>{}, B1{});
       else
-        role(std::false_type{});
+        role(std::false_type{}, B0{});
     }
   } else {
     using H16 = typename std::conditional<(MIX <= 3), __bf16, _Float16>::type;
     constexpr int NPROD = MIX <= 3 ? MIX : MIX - 3;
-    if (h == 0)
-      mixed_wave<N, H16, NPROD, 0, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
-    else
-      mixed_wave<N, H16, NPROD, 1, IL, kFluxIters, RBW>(a, t, mr, lane, rb0, acc, gather, flux_step, flux_store);
+    auto role = [&](auto blocks) {
+      constexpr int NB = decltype(blocks)::value;
+      auto& ac = reinterpret_cast<acc_t(&)[NB][3]>(acc);
+      if (h == 0)
+        mixed_wave<N, H16, NPROD, 0, IL, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
+                                                               flux_store);
+      else
+        mixed_wave<N, H16, NPROD, 1, IL, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
+                                                               flux_store);
+    };
+    if constexpr (ONE_COPY) {
+      role(B0{});
+    } else {
+      if (rh == 1)
+        role(B1{});
+      else
+        role(B0{});
+    }
   }
 
   // Epilogue through LDS: [c][e][i] for the role's three fields (the waves
@@ -863,13 +929,13 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   for (int j = 0; j < kAhead; ++j) rk_load(j);
   __syncthreads();
   T* so = t.su + h * (3 * 16 * Np);
-  constexpr bool TAIL = mfma_tail<N, T, MIX>();
-  const bool tail_wave = TAIL && rb0 + RBW == RB;
+  const bool tail_wave = TAIL && rb0 + nb == RB;
 #pragma unroll
   for (int ib = 0; ib < RBW; ++ib)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      if (ib == RBW - 1 && tail_wave) {
+      if (ib >= nb) continue;
+      if (ib == nb - 1 && tail_wave) {
         // 4-row block: FP64 row q in component 0; FP32 rows r, reduced over
         // the lane groups, written by group 0.
         if constexpr (sizeof(T) == 8) {
@@ -965,9 +1031,44 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
 // constraint).  Set where the unconstrained allocation lands one or two
 // registers past the 168 that three waves per SIMD allow (512 / 3, in
 // granules of 8), which the allocator then meets without spilling.
-template <int N, typename T, int MIX>
+// kCfgOccupancy asks for what the tile's LDS allows (workgroups per CU x
+// waves per workgroup over the 4 SIMDs, at most 8).
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
+constexpr int lds_waves_per_simd() {
+  constexpr size_t tile_bytes = sizeof(MfmaTile<N, T, lift_split<N, T, MIX, CFG>(), false>);
+  constexpr int wg = int((160 * 1024) / tile_bytes);
+  constexpr int w = wg * waves_per_tile<N, T, MIX, CFG>() / 4;
+  return w > 8 ? 8 : (w < 1 ? 1 : w);
+}
+template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int min_waves_per_simd() {
-  return (sizeof(T) == 4 && ((MIX == 0 && N == 6) || (MIX == 2 && N == 4))) ? 3 : 1;
+  constexpr int d = (sizeof(T) == 4 && ((MIX == 0 && N == 6) || (MIX == 2 && N == 4))) ? 3 : 1;
+  return CFG == kCfgOccupancy ? lds_waves_per_simd<N, T, MIX, CFG>() : d;
+}
+
+// Whether tuning configuration CFG is built for (N, T, MIX): the default
+// wherever the kernel is; another only where it changes the kernel and the
+// resulting combination is one the kernel supports (the interleaved flux and
+// the split lift need two waves per tile and exclude each other).
+template <int N, typename T, int MIX, int CFG>
+constexpr bool config_built() {
+  if constexpr (!mfma_supported<N, T, MIX, kCfgDefault>() || !mfma_supported<N, T, MIX, CFG>()) {
+    return false;
+  } else {
+    constexpr int W = waves_per_tile<N, T, MIX, CFG>();
+    constexpr bool IL = flux_interleaved<N, T, MIX, CFG>(), LH = lift_split<N, T, MIX, CFG>();
+    constexpr bool ok = (W == 2 || (!IL && !LH)) && !(IL && LH);
+    if constexpr (CFG == kCfgDefault) return ok;
+    if constexpr (CFG == kCfgWaves) return ok && W != waves_per_tile<N, T, MIX>();
+    if constexpr (CFG == kCfgPrefetch) return ok;
+    if constexpr (CFG == kCfgOccupancy)
+      return ok && lds_waves_per_simd<N, T, MIX, CFG>() > min_waves_per_simd<N, T, MIX>() &&
+             lds_waves_per_simd<N, T, MIX, CFG>() >= 2;
+    if constexpr (CFG == kCfgInterleave) return ok && MIX == 0 && IL != flux_interleaved<N, T, MIX>();
+    if constexpr (CFG == kCfgLift) return ok && MIX == 0 && LH != lift_split<N, T, MIX>();
+    if constexpr (CFG == kCfgTail) return ok && MIX == 0 && mfma_tail<N, T, MIX, CFG>() != mfma_tail<N, T, MIX>();
+    return false;
+  }
 }
 
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous range of the
@@ -977,12 +1078,12 @@ __device__ inline int64_t xcd_tile(int64_t n) {
   return int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <int N, typename T, bool RK, int MIX, bool MAT = false>
-__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>()), (min_waves_per_simd<N, T, MIX>())) void rhs_mfma_kernel(
-    RhsArgs a) {
+template <int N, typename T, bool RK, int MIX, bool MAT = false, int CFG = kCfgDefault>
+__global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX, CFG>()),
+                             (min_waves_per_simd<N, T, MIX, CFG>())) void rhs_mfma_kernel(RhsArgs a) {
   const int64_t tile = xcd_tile((a.K + 15) / 16);
   if (tile >= (a.K + 15) / 16) return;
-  rhs_mfma_tile<N, T, RK, MIX, MAT>(a, tile);
+  rhs_mfma_tile<N, T, RK, MIX, MAT, CFG>(a, tile);
 }
 
 // One Runge-Kutta stage for every problem of a batch that has order N: the
@@ -1026,21 +1127,21 @@ hipError_t launch_rk_mfma_batch(const BatchArgs& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int N, typename T, int MIX = 0, bool MAT = false>
+template <int N, typename T, int MIX = 0, bool MAT = false, int CFG = kCfgDefault>
 hipError_t launch_rhs_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false, MIX, MAT>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s,
-                     a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, false, MIX, MAT, CFG>), dim3(grid),
+                     dim3(64 * waves_per_tile<N, T, MIX, CFG>()), 0, s, a);
   return hipGetLastError();
 }
 
-template <int N, typename T, int MIX = 0, bool MAT = false>
+template <int N, typename T, int MIX = 0, bool MAT = false, int CFG = kCfgDefault>
 hipError_t launch_rk_mfma(const RhsArgs& a, hipStream_t s) {
   const int64_t nt = (a.K + 15) / 16;
   const unsigned grid = unsigned(8 * ((nt + 7) / 8));
-  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true, MIX, MAT>), dim3(grid), dim3(64 * waves_per_tile<N, T, MIX>()), 0, s,
-                     a);
+  hipLaunchKernelGGL((rhs_mfma_kernel<N, T, true, MIX, MAT, CFG>), dim3(grid),
+                     dim3(64 * waves_per_tile<N, T, MIX, CFG>()), 0, s, a);
   return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16x3": DG_BF16X3, "f16x3": DG
 #: every symbol the public headers declare
 EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",
             "dg_destroy", "dg_last_error", "dg_variant_count", "dg_variant_name", "dg_set_variant", "dg_time_rhs",
-            "dg_setup_batch", "dg_batch_problem", "dg_rk_step_batch", "dg_destroy_batch",
+            "dg_setup_batch", "dg_batch_problem", "dg_rk_step_batch", "dg_destroy_batch", "dg_energy",
+            "dg_system_compile", "dg_setup_system",
             "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
 
 
@@ -48,7 +49,8 @@ class Info(C.Structure):
     _fields_ = [("N", C.c_int32), ("Np", C.c_int32), ("Nfp", C.c_int32), ("precision", C.c_int32),
                 ("K", C.c_int64), ("field_stride", C.c_int64), ("state_elems", C.c_int64),
                 ("elem_bytes", C.c_int32), ("tile_elems", C.c_int32), ("dt_cfl1", C.c_double),
-                ("alpha", C.c_double), ("n_boundary_faces", C.c_int64), ("variant", C.c_int32)]
+                ("alpha", C.c_double), ("n_boundary_faces", C.c_int64), ("variant", C.c_int32),
+                ("nfields", C.c_int32)]
 
 
 def _load():
@@ -65,6 +67,9 @@ def _load():
         "dg_info_get": (C.c_int, [P, C.POINTER(Info)]),
         "dg_rhs": (C.c_int, [P, P, P, P]),
         "dg_rk_step": (C.c_int, [P, P, P, C.c_double, C.c_double, C.c_int32, P]),
+        "dg_energy": (C.c_int, [P, P, P, P, P]),
+        "dg_system_compile": (C.c_int, [C.c_char_p, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, P, C.c_int64]),
+        "dg_setup_system": (C.c_int, [C.POINTER(MeshDesc), C.c_char_p, C.c_int32, C.POINTER(P)]),
         "dg_pack": (C.c_int, [P, P, P, P]),
         "dg_unpack": (C.c_int, [P, P, P, P]),
         "dg_nodes": (C.c_int, [P, P]),
@@ -202,6 +207,23 @@ def dg_setup_mesh(N, VX, EToV, precision=DG_FP64, alpha=1.0, face_bc=None, eps=N
     return h
 
 
+def dg_setup_system(N, VX, EToV, source, nfields, precision=DG_FP64, alpha=1.0, face_bc=None, device=-1):
+    d, keep = mesh_desc(N, VX, EToV, precision, alpha, face_bc, None, None, device)
+    h = C.c_void_p()
+    _check(lib.dg_setup_system(C.byref(d), source.encode(), int(nfields), C.byref(h)))
+    del keep
+    return h
+
+
+def dg_system_compile(source, nfields, N, precision=DG_FP64, arch="gfx950"):
+    """Compiles a system's source with hipRTC (no device needed); returns the log."""
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    log = C.create_string_buffer(1 << 16)
+    _check(lib.dg_system_compile(source.encode(), int(nfields), int(N), int(precision), arch.encode(), log, len(log)))
+    return log.value.decode(errors="replace")
+
+
 def dg_info_get(p):
     info = Info()
     _check(lib.dg_info_get(p, C.byref(info)))
@@ -216,6 +238,10 @@ def dg_rk_step(p, u, res, t, dt, nsteps, stream=None):
     _check(lib.dg_rk_step(p, _ptr(u), _ptr(res), float(t), float(dt), int(nsteps), _stream(stream)))
 
 
+def dg_energy(p, u, ref, dev_out, stream=None):
+    _check(lib.dg_energy(p, _ptr(u), _ptr(ref), _ptr(dev_out), _stream(stream)))
+
+
 def dg_pack(p, host_u, dev_u, stream=None):
     host_u = np.ascontiguousarray(host_u, dtype=np.float64)
     _check(lib.dg_pack(p, _ptr(host_u), _ptr(dev_u), _stream(stream)))
@@ -223,7 +249,7 @@ def dg_pack(p, host_u, dev_u, stream=None):
 
 def dg_unpack(p, dev_u, stream=None):
     info = dg_info_get(p)
-    out = np.zeros((6, info.K, info.Np))
+    out = np.zeros((info.nfields, info.K, info.Np))
     _check(lib.dg_unpack(p, _ptr(dev_u), _ptr(out), _stream(stream)))
     return out
 
@@ -312,8 +338,9 @@ class Problem:
     def pack(self, host_u, dev_u=None, stream=None):
         dev_u = self.empty_state() if dev_u is None else self.check_state(dev_u, "dev_u")
         host_u = np.asarray(host_u, dtype=np.float64)
-        if host_u.shape != (6, self.info.K, self.info.Np):
-            raise ValueError(f"host_u must have shape (6, {self.info.K}, {self.info.Np})")
+        shape = (self.info.nfields, self.info.K, self.info.Np)
+        if host_u.shape != shape:
+            raise ValueError(f"host_u must have shape {shape}")
         dg_pack(self.handle, host_u, dev_u, stream)
         return dev_u
 
@@ -328,6 +355,20 @@ class Problem:
 
     def nodes(self):
         return dg_nodes(self.handle)
+
+    def energy(self, u, ref=None, out=None, stream=None):
+        """Discrete (material-weighted) energy of u - ref on the device; returns
+        the one-element float64 device tensor it was written to."""
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device="cuda")
+        dg_energy(self.handle, self.check_state(u, "u"), None if ref is None else self.check_state(ref, "ref"),
+                  out, stream)
+        return out
+
+    def error_norm(self, u, ref, stream=None):
+        """L2 (mass-matrix) norm of u - ref, computed on the device (synchronises)."""
+        return float(2.0 * self.energy(u, ref, stream=stream).item()) ** 0.5
 
     def set_variant(self, v):
         dg_set_variant(self.handle, v)

@@ -1,7 +1,10 @@
 """Summaries of rocprofv3 output for the benchmark's kernels.
 
-``python -m paper_1211_0582_amd.profiling stats <kernel_stats.csv> <out.txt> <command...>``
-    writes the per-kernel duration table of a ``--kernel-trace --stats`` run.
+``python -m paper_1211_0582_amd.profiling stats <kernel_stats.csv | results.db> <out.txt> <command...>``
+    writes the per-kernel duration table of a ``--kernel-trace --stats`` run
+    (from the CSV summary, or from the rocpd database, where launches are
+    grouped by kernel and grid size so that one kernel on meshes of
+    different sizes gives one row per mesh).
 ``python -m paper_1211_0582_amd.profiling traffic <fetch_dir> <write_dir> <out.txt> <substr> <copy_bytes> <command...>``
     writes the HBM traffic per dispatch of the kernels whose name contains
     ``substr``: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two
@@ -40,7 +43,25 @@ def source_hash(csrc: str | None = None) -> str:
     return h.hexdigest()
 
 
+def stats_summary_db(db_path: str, command: str) -> str:
+    import sqlite3
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, grid_x, workgroup_x, count(*), avg(duration), min(duration), max(duration), "
+                       "sum(duration) from kernels group by name, grid_x, workgroup_x order by sum(duration) desc")
+    rows = list(rows)
+    total = sum(r[7] for r in rows) or 1.0
+    out = [f"command: {command}", "", "launches grouped by kernel and launch size (grid lanes / workgroup lanes)", "",
+           f"{'kernel':64s} {'grid':>9s} {'wg':>4s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} "
+           f"{'pct':>6s}"]
+    for name, gx, wx, n, avg, mn, mx, tot in rows:
+        out.append(f"{name[:64]:64s} {gx:>9d} {wx:>4d} {n:>6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f} "
+                   f"{100.0 * tot / total:6.2f}")
+    return "\n".join(out) + "\n"
+
+
 def stats_summary(csv_path: str, command: str) -> str:
+    if csv_path.endswith(".db"):
+        return stats_summary_db(csv_path, command)
     rows = list(csv.DictReader(open(csv_path)))
     out = [f"command: {command}", "", f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
     for r in rows:
