@@ -218,6 +218,19 @@ dg_status dg_time_rhs(dg_problem p, const void* u, void* rhs, int32_t warmup, in
 dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
                      int32_t nsteps, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dg_rk_step
+ * whose second state buffer is a library-static device array of
+ * DG_NOALLOC_SCRATCH_BYTES per device instead of the problem's own scratch.
+ * It calls no allocating routine.  The array is shared by every call on a
+ * device and keeps the last call's contents: calls that overlap on one
+ * device (other streams, other threads) race on it.  Results equal
+ * dg_rk_step's bit for bit.  Errors: as dg_rk_step, DG_EUNSUPPORTED when one
+ * state array (state_elems * elem_bytes) exceeds DG_NOALLOC_SCRATCH_BYTES. */
+#define DG_NOALLOC_SCRATCH_BYTES (256ll << 20)
+dg_status dg_rk_step_noalloc(dg_problem p, void* u, void* res, double t, double dt,
+                             int32_t nsteps, void* stream);
+
 /* ---- Run-time compiled systems (Section 4, run-time code generation) -----
  * A hyperbolic system other than the built-in Maxwell one, given as C++
  * source that defines `struct System` (M fields; volume flux, numerical flux
@@ -237,7 +250,7 @@ dg_status dg_rk_step(dg_problem p, void* u, void* res, double t, double dt,
  * dg_setup_system: as dg_setup_mesh for the system: state arrays hold
  * nfields fields (dg_info.nfields); face_bc codes are passed to
  * System::exterior; eps and mu must be NULL (or all 1).  dg_rhs, dg_rk_step
- * (right-hand side plus the update kernel), dg_energy
+ * (right-hand side plus the update kernel), dg_rk_step_noalloc, dg_energy
  * (sum_k J_k u^T M u / 2 over all fields), dg_pack/dg_unpack ([nfields][K][Np]),
  * dg_time_rhs and dg_destroy apply; batches and dg_set_variant do not.  The
  * compiled module is cached for the process (per device, architecture,

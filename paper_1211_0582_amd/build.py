@@ -53,7 +53,7 @@ def _jobs():
         jobs.append(([CXX, *HOST_FLAGS, "-c", src, "-o", os.path.join(BUILD, name + ".o")], name))
     src = _embed_rtc_source()
     jobs.append(([CXX, *HOST_FLAGS, "-c", src, "-o", os.path.join(BUILD, "rtc_source.o")], "rtc_source.cpp"))
-    for name in ("api.cpp", "batch.cpp", "rtc.cpp", "lserk.hip", "diag.hip"):
+    for name in ("api.cpp", "batch.cpp", "rtc.cpp", "lserk.hip", "noalloc.hip", "diag.hip"):
         src = os.path.join(CSRC, name)
         lang = ["-x", "hip"] if name.endswith(".cpp") else []
         jobs.append(([HIPCC, *HIP_FLAGS, *lang, "-c", src, "-o", os.path.join(BUILD, name + ".o")], name))

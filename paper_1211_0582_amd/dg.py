@@ -23,7 +23,7 @@ PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16x3": DG_BF16X3, "f16x3": DG
 #: every symbol the public headers declare
 EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",
             "dg_destroy", "dg_last_error", "dg_variant_count", "dg_variant_name", "dg_set_variant", "dg_time_rhs",
-            "dg_setup_batch", "dg_batch_problem", "dg_rk_step_batch", "dg_destroy_batch", "dg_energy",
+            "dg_setup_batch", "dg_batch_problem", "dg_rk_step_batch", "dg_destroy_batch", "dg_rk_step_noalloc", "dg_energy",
             "dg_system_compile", "dg_setup_system",
             "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
 
@@ -67,6 +67,7 @@ def _load():
         "dg_info_get": (C.c_int, [P, C.POINTER(Info)]),
         "dg_rhs": (C.c_int, [P, P, P, P]),
         "dg_rk_step": (C.c_int, [P, P, P, C.c_double, C.c_double, C.c_int32, P]),
+        "dg_rk_step_noalloc": (C.c_int, [P, P, P, C.c_double, C.c_double, C.c_int32, P]),
         "dg_energy": (C.c_int, [P, P, P, P, P]),
         "dg_system_compile": (C.c_int, [C.c_char_p, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, P, C.c_int64]),
         "dg_setup_system": (C.c_int, [C.POINTER(MeshDesc), C.c_char_p, C.c_int32, C.POINTER(P)]),
@@ -236,6 +237,10 @@ def dg_rhs(p, u, rhs, stream=None):
 
 def dg_rk_step(p, u, res, t, dt, nsteps, stream=None):
     _check(lib.dg_rk_step(p, _ptr(u), _ptr(res), float(t), float(dt), int(nsteps), _stream(stream)))
+
+
+def dg_rk_step_noalloc(p, u, res, t, dt, nsteps, stream=None):
+    _check(lib.dg_rk_step_noalloc(p, _ptr(u), _ptr(res), float(t), float(dt), int(nsteps), _stream(stream)))
 
 
 def dg_energy(p, u, ref, dev_out, stream=None):
