@@ -263,6 +263,43 @@ def bench_batch(args, torch, dg):
     print(json.dumps(line), flush=True)
 
 
+def systems_rhs(torch, k, N, prec, reps):
+    """Run-time compiled systems (acoustics, Euler) on the k^3 x 6 cube: one
+    right-hand side timed by dg_time_rhs, priced against the binding roofline
+    from the contraction flops 2 M Np (3 Np + 4 Nfp) and the bytes of one state
+    read, one written, geometry and connectivity per element."""
+    from paper_1211_0582_amd import dg
+    from paper_1211_0582_amd import systems as S
+    out = {}
+    VX, EToV = I.kuhn_cube(k, 0.1, 0)
+    for spec in (S.acoustics(), S.euler()):
+        t0 = time.perf_counter()
+        p = S.SystemProblem(spec, N, VX, EToV, prec)
+        setup_s = time.perf_counter() - t0
+        K, Np, Nfp, M, sz = p.info.K, p.info.Np, p.info.Nfp, spec.M, p.info.elem_bytes
+        xyz = p.nodes()
+        u = np.ones((M, K, Np)) + I.field_noise((M, K, Np), 1e-2, 1)
+        if spec.name == "euler":
+            u[1:4] *= 0.1
+            u[4] = 2.5 + 0.1 * np.cos(xyz[..., 0])
+        du = p.pack(u)
+        o = p.zeros_state()
+        t = dg.dg_time_rhs(p.handle, du, o, 3, reps) / 1e3
+        flops = 2 * M * Np * (3 * Np + 4 * Nfp) * K
+        nbytes = (2 * M * Np * sz + 25 * sz + 16) * K
+        peak_f = (PEAKS["fp64_TFs"] if prec == "fp64" else PEAKS["fp32_TFs"]) * 1e12
+        if flops / peak_f >= nbytes / (PEAKS["hbm_GBs"] * 1e9):
+            bound, ach, peak, unit = "mfma", flops / t / 1e12, peak_f / 1e12, "TFLOP/s"
+        else:
+            bound, ach, peak, unit = "hbm", nbytes / t / 1e9, PEAKS["hbm_GBs"], "GB/s"
+        out[spec.name] = {"K": K, "N": N, "fields": M, "rhs_us": 1e6 * t, "gdofs": M * K * Np / t / 1e9,
+                          "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                          "setup_and_compile_s": setup_s}
+        p.close()
+        del du, o
+    return out
+
+
 MIX = {"fp64": 0, "fp32": 0, "bf16": 1, "bf16x2": 2, "bf16x3": 3, "f16": 4, "f16x2": 5, "f16x3": 6}
 
 
@@ -297,15 +334,16 @@ def measure(torch, dg, profiling, k, N, prec, steps, warmup, rhs_reps, variant=N
     t_stage = t_total / (5 * steps)   # average fused-stage launch in the timed region
     dofs = 6 * K * Np
     tname = "double" if prec == "fp64" else "float"
-    if p.variant == "mfma":
-        kname = f"void dgd::rhs_mfma_kernel<{N}, {tname}, true, {MIX[prec]}, false>(dgd::RhsArgs)"
-        kname_rhs = f"void dgd::rhs_mfma_kernel<{N}, {tname}, false, {MIX[prec]}, false>(dgd::RhsArgs)"
+    if p.variant.startswith("mfma"):
+        cfg = dg.variant_id(p.variant) - dg.variant_id("mfma")   # tuning configuration of the kernel
+        kname = f"void dgd::rhs_mfma_kernel<{N}, {tname}, true, {MIX[prec]}, false, {cfg}>(dgd::RhsArgs)"
+        kname_rhs = f"void dgd::rhs_mfma_kernel<{N}, {tname}, false, {MIX[prec]}, false, {cfg}>(dgd::RhsArgs)"
     else:
         kname = kname_rhs = f"void dgd::rhs_valu_kernel<{N}, {tname}>(dgd::RhsArgs)"
     traffic_file = traffic_file or os.path.join(ROOT, "profiles", f"rhs_traffic_k{k}_n{N}.txt")
     traffic = profiling.read_traffic(traffic_file, kname)
     bound, achieved, peak, unit = roofline(prec, N, K, t_stage, s, stage=True)
-    if prec in ("fp64", "fp32") and p.variant != "mfma":
+    if prec in ("fp64", "fp32") and not p.variant.startswith("mfma"):
         bound = "alu"
     rb, ra, rp, ru = roofline(prec, N, K, t_rhs, s)
     r = {
@@ -434,6 +472,10 @@ def main():
                                           "PEC cavity + noise, upwind, LSERK(5,4) step", "precisions": small}
         print("bench: 64-problem batch", file=sys.stderr, flush=True)
         line["batch"] = batch_modes(torch, dg, args.steps, args.warmup)
+        print("bench: run-time compiled systems", file=sys.stderr, flush=True)
+        line["compiled_systems"] = {"workload": "jittered Kuhn cube 24^3x6 tets (K=82944), N=5, FP32, one RHS "
+                                                "of a system compiled at run time from its flux description",
+                                    "systems": systems_rhs(torch, 24, 5, "fp32", args.rhs_reps)}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(24 if k >= 24 else k, N, 12 if k >= 24 else max(2, k // 2))

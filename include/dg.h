@@ -183,7 +183,9 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
  *                        block holds at most 4 nodes).
  * Variants 2..7 exist where they give a different kernel (FP64, FP32 and the
  * x3 split forms, vacuum flux); batches use "mfma".  dg_setup_mesh picks
- * "mfma" where it is built for (N, precision), else "valu".
+ * the variant the library's tuning table (the autotuner's measurements on
+ * gfx950, compiled in) records for (precision, N, K below or from 20000
+ * elements) where it is built, else "mfma" where built, else "valu".
  * dg_variant_name returns NULL outside 0 .. dg_variant_count()-1.
  * dg_set_variant: DG_EINVAL (null p, v out of range), DG_EUNSUPPORTED (not
  * built for this order, precision and flux form; the problem keeps its
@@ -191,6 +193,14 @@ dg_status dg_rhs(dg_problem p, const void* u, void* rhs, void* stream);
 int32_t dg_variant_count(void);
 const char* dg_variant_name(int32_t v);
 dg_status dg_set_variant(dg_problem p, int32_t v);
+
+/* Order in which the matrix-core kernels take the 16-element tiles (the
+ * paper's tuning of the element blocks the flux gather works on, Section 4):
+ * enable != 0 (the default) walks the tiles in the Morton order of their
+ * centroids, so the tiles an XCD holds at one time are spatial neighbours
+ * and their neighbour-trace reads hit its L2; 0 walks them in element order.
+ * Results are bitwise identical either way.  Errors: DG_EINVAL (null p). */
+dg_status dg_set_tile_order(dg_problem p, int32_t enable);
 
 /* Timing core of the autotuner (the paper's automated tuning, Section 4):
  * runs dg_rhs(p, u, rhs) `warmup` times, then `reps` times between two HIP

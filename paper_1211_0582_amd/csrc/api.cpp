@@ -4,6 +4,7 @@
 // lserk.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -16,6 +17,7 @@
 #include "device_common.hpp"
 #include "host_common.hpp"
 #include "problem.hpp"
+#include "tuning_table.hpp"
 
 using namespace dgh;
 
@@ -114,6 +116,7 @@ void free_problem(dg_problem p) {
   hipFree(p->d_mass);
   hipFree(p->d_weight);
   hipFree(p->d_partial);
+  hipFree(p->d_tile_order);
   delete p;
 }
 
@@ -139,6 +142,51 @@ std::vector<double> material_records(const HostMesh& hm, const double* eps, cons
     }
   }
   return rec;
+}
+
+// Tile order: the 16-element tiles sorted by the Morton code of their
+// centroids (bounding box quantised to 2^10 cells per axis), so that tiles
+// processed at the same time are spatial neighbours.
+dg_status upload_tile_order(dg_problem p) {
+  const int64_t nt = (p->K + 15) / 16;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  std::vector<double> cen(static_cast<size_t>(nt) * 3, 0.0);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t k0 = t * 16, k1 = std::min<int64_t>(p->K, k0 + 16);
+    for (int64_t k = k0; k < k1; ++k)
+      for (int v = 0; v < 4; ++v)
+        for (int d = 0; d < 3; ++d) cen[size_t(t) * 3 + d] += p->verts[size_t(k) * 12 + v * 3 + d];
+    for (int d = 0; d < 3; ++d) {
+      double& c = cen[size_t(t) * 3 + d];
+      c /= double(4 * (k1 - k0));
+      lo[d] = std::min(lo[d], c);
+      hi[d] = std::max(hi[d], c);
+    }
+  }
+  auto spread = [](uint64_t x) {  // 10 bits -> every third bit of 30
+    x &= 0x3ff;
+    x = (x | (x << 16)) & 0x30000ff;
+    x = (x | (x << 8)) & 0x300f00f;
+    x = (x | (x << 4)) & 0x30c30c3;
+    x = (x | (x << 2)) & 0x9249249;
+    return x;
+  };
+  std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(nt));
+  for (int64_t t = 0; t < nt; ++t) {
+    uint64_t m = 0;
+    for (int d = 0; d < 3; ++d) {
+      const double w = hi[d] > lo[d] ? (cen[size_t(t) * 3 + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+      m |= spread(uint64_t(std::min(1023.0, std::max(0.0, w * 1024.0)))) << d;
+    }
+    key[size_t(t)] = {m, int32_t(t)};
+  }
+  std::stable_sort(key.begin(), key.end());
+  std::vector<int32_t> order(static_cast<size_t>(nt));
+  for (int64_t t = 0; t < nt; ++t) order[size_t(t)] = key[size_t(t)].second;
+  DG_HIP(hipMalloc(&p->d_tile_order, order.size() * sizeof(int32_t)), "hipMalloc(tile order)");
+  DG_HIP(hipMemcpy(p->d_tile_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+         "upload tile order");
+  return DG_OK;
 }
 
 // Diagnostics data: M = (V V^T)^-1, J eps and J mu per element, partial sums.
@@ -287,6 +335,7 @@ dgd::RhsArgs rhs_args(dg_problem p, const void* u, void* rhs) {
   a.rk_a = a.rk_b = a.rk_dt = 0.0;
   // u read, rhs written.
   a.stream_out = 2 * p->state_elems * p->elem_bytes > kLastLevelCacheBytes;
+  a.tile_order = p->use_tile_order ? p->d_tile_order : nullptr;
   return a;
 }
 
@@ -496,6 +545,15 @@ dg_status setup_problem_impl(const dg_mesh_desc* desc, int nfields, bool system,
       delete p;
       return fail(DG_EUNSUPPORTED, "no kernel for this order and precision");
     }
+    // The autotuner's winner for (precision, N, size bucket), where built.
+    const int tv = material ? -1 : dgd::tuned_variant(desc->precision, desc->N, desc->K);
+    if (tv >= 0) {
+      const dgd::KernelSet k = dgd::kernels(desc->N, desc->precision, tv, false);
+      if (k.rhs) {
+        p->variant = tv;
+        p->ks = k;
+      }
+    }
     p->tile = p->ks.tile;
   }
   p->device = dev;
@@ -506,6 +564,7 @@ dg_status setup_problem_impl(const dg_mesh_desc* desc, int nfields, bool system,
   const std::vector<double> mat = material ? material_records(hm, desc->eps, desc->mu, desc->alpha) : std::vector<double>();
   st = (p->precision == DG_FP64) ? upload<double>(p, *re, hm, mat) : upload<float>(p, *re, hm, mat);
   if (st == DG_OK) st = upload_diag(p, *re, hm, desc->eps, desc->mu);
+  if (st == DG_OK) st = upload_tile_order(p);
   if (st != DG_OK) {
     free_problem(p);
     return st;
@@ -559,6 +618,13 @@ dg_status dg_set_variant(dg_problem p, int32_t v) {
   p->variant = v;
   p->ks = k;
   p->tile = k.tile;
+  return DG_OK;
+}
+
+dg_status dg_set_tile_order(dg_problem p, int32_t enable) {
+  clear_error();
+  if (!p) return fail(DG_EINVAL, "null problem");
+  p->use_tile_order = enable != 0;
   return DG_OK;
 }
 

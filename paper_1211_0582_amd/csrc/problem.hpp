@@ -26,6 +26,8 @@ struct dg_problem_s {
   double* d_mass = nullptr;     // reference mass matrix M (Np x Np, binary64) for the diagnostics
   double* d_weight = nullptr;   // K x 2: J eps, J mu per element
   double* d_partial = nullptr;  // per-block partial sums of the diagnostics
+  int32_t* d_tile_order = nullptr;  // Morton order of the 16-element tiles' centroids
+  bool use_tile_order = true;
   std::vector<double> verts;  // K x 4 x 3 vertex coordinates (for dg_nodes)
   int variant = 0;
   dgd::KernelSet ks;

@@ -1078,11 +1078,16 @@ __device__ inline int64_t xcd_tile(int64_t n) {
   return int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
+// With a tile order (a space-filling-curve order of the tiles' centroids),
+// the XCD-contiguous slots walk it instead of the element numbering, so the
+// tiles resident on one XCD at a time are spatial neighbours and their
+// neighbour-trace gathers hit that XCD's L2.
 template <int N, typename T, bool RK, int MIX, bool MAT = false, int CFG = kCfgDefault>
 __global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX, CFG>()),
                              (min_waves_per_simd<N, T, MIX, CFG>())) void rhs_mfma_kernel(RhsArgs a) {
-  const int64_t tile = xcd_tile((a.K + 15) / 16);
+  int64_t tile = xcd_tile((a.K + 15) / 16);
   if (tile >= (a.K + 15) / 16) return;
+  if (a.tile_order) tile = a.tile_order[tile];
   rhs_mfma_tile<N, T, RK, MIX, MAT, CFG>(a, tile);
 }
 
@@ -1105,6 +1110,7 @@ __global__ __launch_bounds__((64 * waves_per_tile<N, T, MIX>()), (min_waves_per_
   a.geo = P.geo;
   a.conn = P.conn;
   a.mat = nullptr;
+  a.tile_order = nullptr;
   a.ops = nullptr;
   a.ops_frag = b.ops_frag;
   a.ops_frag16 = b.ops_frag16;

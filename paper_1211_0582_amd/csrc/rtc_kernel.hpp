@@ -155,8 +155,10 @@ __device__ inline void tile_rhs(const Args& a, int64_t tile) {
       for (int c = 0; c < NC; ++c) acc[ib][c] = acc_t{0, 0, 0, 0};
     auto frag = [&](int kg, int ib) { return load<T>(rf, uint32_t(((ib * KS + kg) * 64) + lane) * sz); };
 
-    // Volume: X_d = -sum_x m_{d,x} F_x(u) at node j = 4 ks + q of element e
-    // (padded depth rows j >= Np hold zeros and meet zero operator columns).
+    // Volume: X_d = -sum_x m_{d,x} F_x(u) at node j = 4 ks + q of element e.
+    // Padded depth rows j >= Np meet zero operator columns, but a nonlinear
+    // flux of their zero fields need not be finite (0 / 0), and 0 x NaN is
+    // NaN in the product: their operand is set to zero.
 #pragma unroll
     for (int ks = 0; ks < KSV; ++ks) {
       const int j = 4 * ks + q;
@@ -168,6 +170,10 @@ __device__ inline void tile_rhs(const Args& a, int64_t tile) {
         const T md[3] = {mr[3 * d], mr[3 * d + 1], mr[3 * d + 2]};
         T x[M];
         Sys::template volume<T>(md, uv, x);
+        if (j >= Np) {
+#pragma unroll
+          for (int c = 0; c < M; ++c) x[c] = T(0);
+        }
         T av[RB];
 #pragma unroll
         for (int ib = 0; ib < RB; ++ib) av[ib] = frag(d * KSV + ks, ib);

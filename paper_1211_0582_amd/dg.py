@@ -24,7 +24,7 @@ PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16x3": DG_BF16X3, "f16x3": DG
 EXPORTED = ("dg_setup_mesh", "dg_info_get", "dg_rhs", "dg_rk_step", "dg_pack", "dg_unpack", "dg_nodes",
             "dg_destroy", "dg_last_error", "dg_variant_count", "dg_variant_name", "dg_set_variant", "dg_time_rhs",
             "dg_setup_batch", "dg_batch_problem", "dg_rk_step_batch", "dg_destroy_batch", "dg_rk_step_noalloc", "dg_energy",
-            "dg_system_compile", "dg_setup_system",
+            "dg_system_compile", "dg_setup_system", "dg_set_tile_order",
             "dg_host_ref_nodes", "dg_host_ref_operators", "dg_host_mesh")
 
 
@@ -79,6 +79,7 @@ def _load():
         "dg_variant_count": (C.c_int32, []),
         "dg_variant_name": (C.c_char_p, [C.c_int32]),
         "dg_set_variant": (C.c_int, [P, C.c_int32]),
+        "dg_set_tile_order": (C.c_int, [P, C.c_int32]),
         "dg_time_rhs": (C.c_int, [P, P, P, C.c_int32, C.c_int32, P, C.POINTER(C.c_double)]),
         "dg_setup_batch": (C.c_int, [C.c_int32, C.POINTER(MeshDesc), C.POINTER(P)]),
         "dg_batch_problem": (C.c_int, [P, C.c_int32, C.POINTER(P)]),
@@ -306,7 +307,7 @@ class Problem:
 
     def __init__(self, N, VX, EToV, precision="fp64", alpha=1.0, tuned=False, face_bc=None, eps=None, mu=None,
                  device=-1):
-        """tuned: apply the variant the autotuner cache holds for (N, precision).
+        """tuned: apply the variant the autotuner cache holds for (N, precision, size).
         face_bc: (K, 4) boundary condition codes (DG_BC_*), eps / mu: per-element
         material (scalar or (K,)), device: HIP device ordinal (-1: current)."""
         self.handle = None
@@ -314,7 +315,7 @@ class Problem:
         self.info = dg_info_get(self.handle)
         if tuned:
             from . import autotune
-            v = autotune.lookup(N, self.info.precision)
+            v = autotune.lookup(N, self.info.precision, self.info.K)
             if v is not None:
                 self.set_variant(v)
 
@@ -374,6 +375,9 @@ class Problem:
     def error_norm(self, u, ref, stream=None):
         """L2 (mass-matrix) norm of u - ref, computed on the device (synchronises)."""
         return float(2.0 * self.energy(u, ref, stream=stream).item()) ** 0.5
+
+    def set_tile_order(self, enable: bool):
+        _check(lib.dg_set_tile_order(self.handle, int(bool(enable))))
 
     def set_variant(self, v):
         dg_set_variant(self.handle, v)

@@ -11,6 +11,13 @@
     ``--pmc`` runs, each scaled by what the same counter reads for a plain
     copy of ``copy_bytes`` bytes in the same run.
 
+``python -m paper_1211_0582_amd.profiling counters <dir> <out.txt> <substr> <command...>``
+    writes, per kernel and launch size, the matrix-core busy fraction, the
+    mean waves per SIMD, VALU and MFMA instructions per dispatch, and the
+    HBM bytes from the 32-byte-granular EA counters, from one or more
+    ``--pmc`` runs (SQ counters are summed over all SIMDs, GRBM_GUI_ACTIVE
+    over the 8 XCDs).
+
 The traffic summary records a hash of the kernel sources; ``bench.py`` only
 reports the traffic while the sources still hash to that value.
 """
@@ -115,6 +122,44 @@ def traffic_summary(fetch_dir, write_dir, substr, copy_bytes, command):
     return "\n".join(out) + "\n"
 
 
+SIMDS = 256 * 4   # MI355X: 256 CUs x 4 SIMDs
+XCDS = 8
+
+
+def counters_summary(dirs, substr, command):
+    per = {}
+    for d in dirs:
+        for r in _counter_rows(d):
+            if substr not in r["Kernel_Name"]:
+                continue
+            key = (r["Kernel_Name"], r.get("Grid_Size", ""))
+            per.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = [f"command: {command}", f"source_sha256: {source_hash()}",
+           "normalisation: SQ_* summed over all 1024 SIMDs (SQ_WAVE_CYCLES in quad-cycles), GRBM_GUI_ACTIVE summed "
+           "over the 8 XCDs; HBM bytes = 32 x TCC_EA0_RDREQ_DRAM_32B_sum / TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", ""]
+    for (name, grid), c in sorted(per.items()):
+        m = {k: sum(v) / len(v) for k, v in c.items()}
+        out.append(f"kernel: {name}  (grid {grid}, {max(len(v) for v in c.values())} dispatches)")
+        gui = m.get("GRBM_GUI_ACTIVE")
+        if gui:
+            cyc = gui / XCDS
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in m:
+                out.append(f"  mfma_busy_fraction: {m['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * SIMDS):.4f}")
+            if "SQ_WAVE_CYCLES" in m:
+                out.append(f"  mean_waves_per_simd: {4 * m['SQ_WAVE_CYCLES'] / (cyc * SIMDS):.3f}")
+            out.append(f"  kernel_cycles: {cyc:.0f}")
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_WAVES"):
+            if k in m:
+                out.append(f"  {k.lower()}_per_dispatch: {m[k]:.0f}")
+        if "TCC_EA0_RDREQ_DRAM_32B_sum" in m:
+            out.append(f"  hbm_read_bytes_per_dispatch: {32 * m['TCC_EA0_RDREQ_DRAM_32B_sum']:.0f}")
+        if "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum" in m:
+            out.append(f"  hbm_write_bytes_per_dispatch: {32 * m['TCC_EA0_WRREQ_WRITE_DRAM_32B_sum']:.0f}")
+        if "TCC_EA0_RDREQ_128B_sum" in m and m.get("TCC_EA0_RDREQ_sum"):
+            out.append(f"  read_requests_128B_fraction: {m['TCC_EA0_RDREQ_128B_sum'] / m['TCC_EA0_RDREQ_sum']:.4f}")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path: str, kernel_name: str):
     """Traffic per dispatch of ``kernel_name`` from a summary, or None when the
     summary is missing, lacks the kernel, or was taken on other sources."""
@@ -137,6 +182,8 @@ def main(argv):
         open(argv[2], "w").write(stats_summary(argv[1], " ".join(argv[3:])))
     elif argv[0] == "traffic":
         open(argv[3], "w").write(traffic_summary(argv[1], argv[2], argv[4], float(argv[5]), " ".join(argv[6:])))
+    elif argv[0] == "counters":
+        open(argv[2], "w").write(counters_summary(argv[1].split(","), argv[3], " ".join(argv[4:])))
     else:
         raise SystemExit(__doc__)
 

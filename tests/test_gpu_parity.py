@@ -225,13 +225,44 @@ def test_padding_is_never_read_and_runs_are_deterministic(dg, variant):
     assert _rel(ra, ref) < 1e-12
 
 
+TUNING_VARIANTS = ("mfma_waves", "mfma_prefetch", "mfma_occupancy", "mfma_interleave", "mfma_lift", "mfma_tail")
+
+
+@pytest.mark.parametrize("variant", TUNING_VARIANTS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "f16x3", "bf16x3"])
+@pytest.mark.parametrize("N", range(1, 10))
+def test_every_tuning_variant_matches_the_oracle(dg, N, precision, variant):
+    """Each tuning configuration of the matrix-core kernel (the autotuner's
+    search space) gives the operator to the precision's tolerance, in the
+    right-hand side and in a fused LSERK step."""
+    import torch
+    VX, EToV, m, u, ref = _case(N, 2)
+    p = _problem(dg, N, VX, EToV, precision, variant)
+    _say(f"[gpu] tuning variant {variant} N={N} {precision}")
+    du = p.pack(u)
+    out = p.zeros_state()
+    p.rhs(du, out)
+    torch.cuda.synchronize()
+    got = p.unpack(out)
+    tol = dict(TOL, **SPLIT_TOL)[precision] * (max(1.0, N / 4) if precision in SPLIT_TOL else 1.0)
+    assert _rel(got, ref) < tol
+    dt = D.dt_cfl(m, 0.5)
+    step_ref = L.integrate(lambda v, t: Mx.rhs(m, v), u, 0.0, dt, 1)
+    res = p.zeros_state()
+    p.rk_step(du, res, 0.0, dt, 1)
+    torch.cuda.synchronize()
+    assert _rel(p.unpack(du), step_ref) < {"fp64": 1e-12, "fp32": 1e-5}.get(precision, 1e-3)
+    p.close()
+
+
 def test_variants_agree_and_default(dg):
     import torch
     VX, EToV, m, u, ref = _case(4, 2)
     p = dg.Problem(4, VX, EToV, "fp64")
-    assert p.variant == "mfma"
+    from paper_1211_0582_amd import autotune
+    assert p.variant == (autotune.lookup(4, "fp64", p.info.K, arch="gfx950") or "mfma")
     with pytest.raises(dg.DgError) as e:
-        p.set_variant(7)
+        p.set_variant(dg.dg_variant_count())
     assert e.value.status == dg.DG_EINVAL
     p.close()
     p = dg.Problem(9, VX, EToV, "fp64")       # FP64 at N = 9: only the vector kernel is built
