@@ -278,34 +278,36 @@ dg_status upload(dg_problem p, const RefElement& re, const HostMesh& hm, const s
   DG_HIP(hipMalloc(&p->d_frag, frag.size() * sizeof(T)), "hipMalloc(fragments)");
   DG_HIP(hipMemcpy(p->d_frag, frag.data(), frag.size() * sizeof(T), hipMemcpyHostToDevice), "upload fragments");
 
-  // 16x16x16 fragments of the split precisions: row block ib, depth step s,
-  // lane l holds for v = 0..3 the head and tail of Op[16 ib + l % 16][kappa],
-  // kappa = 16 s + 4 (l / 16) + v; depth = 3 volume blocks of Np4 padded to 16,
-  // then LIFT padded to 16.
+  // 16x16x32 fragments of the split precisions: row block ib, step st, lane
+  // l holds for v = 0..7 the heads (16 bytes) and, 1 KB further on, the tails
+  // of Op[16 ib + l % 16][k], k = 8 (l / 16) + v within the step.  Steps
+  // st = d KV + ks cover nodes 32 ks + k of direction d, steps 3 KV + ls the
+  // lift's face nodes 32 ls + k; rows and columns past Np or NF are zero.
   if (p->precision >= DG_BF16X3) {
     const bool bf = p->precision == DG_BF16X3 || p->precision == DG_BF16 || p->precision == DG_BF16X2;
-    const int KV = (3 * Np4 + 15) / 16 * 16, KL = (NF + 15) / 16 * 16, ST = (KV + KL) / 16;
-    std::vector<uint16_t> f16(size_t(RB) * ST * 64 * 8, 0);
+    const int KV = (Np + 31) / 32, KL = (NF + 31) / 32, ST = 3 * KV + KL;
+    std::vector<uint16_t> f16(size_t(RB) * ST * 2 * 64 * 8, 0);
     for (int ib = 0; ib < RB; ++ib)
       for (int st = 0; st < ST; ++st)
         for (int l = 0; l < 64; ++l)
-          for (int v = 0; v < 4; ++v) {
-            const int row = 16 * ib + (l & 15);
-            const int kap = 16 * st + 4 * (l >> 4) + v;
+          for (int v = 0; v < 8; ++v) {
+            const int row = 16 * ib + (l & 15), k = 8 * (l >> 4) + v;
             double val = 0.0;
             if (row < Np) {
-              if (kap < KV) {
-                if (kap < 3 * Np4 && kap % Np4 < Np) val = (*D[kap / Np4])(row, kap % Np4);
-              } else if (kap - KV < NF) {
-                val = re.LIFT(row, kap - KV);
+              if (st < 3 * KV) {
+                const int j = 32 * (st % KV) + k;
+                if (j < Np) val = (*D[st / KV])(row, j);
+              } else {
+                const int m = 32 * (st - 3 * KV) + k;
+                if (m < NF) val = re.LIFT(row, m);
               }
             }
             const uint16_t hi = bf ? float_to_bf16(float(val)) : float_to_f16(float(val));
             const float hv = bf ? bf16_to_float(hi) : f16_to_float(hi);
             const uint16_t lo = bf ? float_to_bf16(float(val - double(hv))) : float_to_f16(float(val - double(hv)));
-            const size_t base = ((size_t(ib) * ST + st) * 64 + l) * 8;
+            const size_t base = ((size_t(ib) * ST + st) * 2 * 64 + l) * 8;
             f16[base + v] = hi;
-            f16[base + 4 + v] = lo;
+            f16[base + 64 * 8 + v] = lo;
           }
     DG_HIP(hipMalloc(&p->d_frag16, f16.size() * 2), "hipMalloc(16-bit fragments)");
     DG_HIP(hipMemcpy(p->d_frag16, f16.data(), f16.size() * 2, hipMemcpyHostToDevice), "upload 16-bit fragments");

@@ -38,7 +38,7 @@ KernelSet make_mfma(bool material) {
     if (k.rhs) {
       k.tile = 16;
       k.frag_count = MfmaShape<N>::frag_count;
-      k.frag16_bytes = MIX ? MixedShape<N>::frag_bytes : 0;
+      k.frag16_bytes = MIX ? SplitShape<N>::frag_bytes : 0;
     }
   }
   return k;

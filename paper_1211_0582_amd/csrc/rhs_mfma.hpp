@@ -28,6 +28,9 @@
 //    u_out <- u + b res is applied there (u_out is a second state buffer, as
 //    neighbours still read u during the stage).  FP64 launches past the
 //    last-level cache store through streaming stores.
+//  * The split 16-bit forms (split_wave) contract the fields themselves on
+//    16x16x32 MFMAs and apply the metric after each direction's contraction;
+//    fields and fluxes are split into heads and tails once per tile, in LDS.
 //  * Tiles are mapped to workgroups so that each of the 8 XCDs gets a
 //    contiguous range of elements (neighbours then share that XCD's L2).
 #pragma once
@@ -91,12 +94,9 @@ struct MfmaShape {
   static constexpr int KSV = Np4 / 4;         // depth steps per direction
   static constexpr int KSL = NF / 4;          // depth steps of LIFT (4 Nfp is a multiple of 4)
   static constexpr int KS = 3 * KSV + KSL;
-  // LDS row strides: field rows TS = 17 (16 elements + 1, so that the
-  // tile store, which walks consecutive rows of one element, spreads over
-  // the banks); flux rows TQ = 16 (written and read 64 entries at a time in
-  // row order, conflict-free without padding, and one workgroup more fits
-  // per CU at N = 3, 4).
-  static constexpr int TS = 17, TQ = 16;
+  // LDS row strides: 16 elements + 1, so that the tile store and the flux
+  // store, which walk consecutive rows of one element, spread over the banks.
+  static constexpr int TS = 17, TQ = 17;
   static constexpr int frag_count = RB * KS * 64;
   // The LDS tile holds the fields [c][Np4][TS] first, then the fluxes
   // [c][NF][TQ], then the output staging [c][16][Np].
@@ -113,6 +113,32 @@ struct MfmaShape {
     const int f = half ? 6 * HB * TQ : FLUXES;
     return FIELDS > f ? (FIELDS > STAGE ? FIELDS : STAGE) : (f > STAGE ? f : STAGE);
   }
+};
+
+// LDS rows of the split forms: one row per (component, element) holding the
+// row's values in 8-value records (a row of 8 J8 values, then a 16-byte pad
+// so that the 16 elements of a lane group hit distinct banks).  A record is
+// written in FP32 and then replaced, in place or in a second region, by its
+// 8 heads (16 bytes) and 8 tails (16 bytes): one record is one B operand.
+template <int N>
+struct SplitShape {
+  using S = MfmaShape<N>;
+  static constexpr int KV = (S::Np + 31) / 32;  // volume depth steps per direction
+  static constexpr int KL = (S::NF + 31) / 32;  // lift depth steps
+  static constexpr int ST = 3 * KV + KL;        // operator steps (direction-major, then lift)
+  static constexpr int J8 = (S::Np + 7) / 8;    // records per field row
+  static constexpr int J8F = (S::NF + 7) / 8;   // records per flux row
+  static constexpr int RSV = 8 * J8 + 4, RSF = 8 * J8F + 4;  // row strides (floats)
+  // The flux reads its own traces from the FP32 field rows, which are kept
+  // beside the split records where both fit in 80 KB (N <= 6); beyond that the
+  // records replace them in place and the own traces come from global memory
+  // with the neighbour traces.
+  static constexpr bool INPLACE = 2 * 96 * RSV * 4 > 80 * 1024;
+  static constexpr int SPLIT = INPLACE ? 0 : 96 * RSV;  // offset of the split field records
+  static constexpr int max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+  static constexpr int TILE = max3(SPLIT + 96 * RSV, 96 * RSF, 96 * S::Np);
+  // operator fragments: [row block][step][head, tail][lane] x 16 bytes
+  static constexpr int frag_bytes = S::RB * ST * 2 * 64 * 16;
 };
 
 // Tuning configurations of the matrix-core kernels: the autotuner's search
@@ -143,9 +169,11 @@ enum : int {
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int waves_per_tile() {
   constexpr int RB = MfmaShape<N>::RB;
-  // The split forms pay for the duplicated operand split; measured on
-  // MI355X four waves win from N = 5 for FP64/FP32 and from N = 6 for them.
-  constexpr int min_rb = MIX == 0 ? 4 : 6;
+  // Four waves from RB = 4 (N = 5) for FP64 / FP32 (measured on MI355X);
+  // from RB = 2 for the split forms, whose flux phase with two waves per
+  // tile (11 flux iterations per lane at N = 5) needs more registers than
+  // one wave per SIMD allows.
+  constexpr int min_rb = MIX == 0 ? 4 : 2;
   constexpr int d = RB >= min_rb ? 4 : 2;
   if constexpr (CFG == kCfgWaves) return d == 4 ? 2 : (RB >= 2 ? 4 : 2);
   return d;
@@ -179,18 +207,20 @@ constexpr bool mfma_tail() {
   return CFG == kCfgTail ? (fits && !d) : d;
 }
 
-template <int N, typename T>
+template <int N, typename T, int MIX = 0>
 constexpr size_t mfma_lds_bytes() {
-  return size_t(MfmaShape<N>::TILE) * sizeof(T);
+  return MIX ? size_t(SplitShape<N>::TILE) * 4 : size_t(MfmaShape<N>::TILE) * sizeof(T);
 }
 
 // Whether the MFMA variant is built for (N, T): the LDS tile and the
-// accumulators (row blocks per wave x 3 x 4 scalars per lane, at most 144
-// registers) must fit.
+// accumulators must fit -- row blocks per wave x 3 x 4 scalars per lane, at
+// most 144 registers, plus for the split forms the per-direction partial
+// products of up to two blocks.
 template <int N, typename T, int MIX = 0, int CFG = kCfgDefault>
 constexpr bool mfma_supported() {
   constexpr int RBW = row_blocks_first<N, T, MIX, CFG>();
-  return mfma_lds_bytes<N, T>() <= 160 * 1024 && RBW * 3 * 4 * sizeof(T) / 4 <= 144;
+  constexpr int acc = RBW * 3 * 4 * int(sizeof(T)) / 4 + (MIX ? (RBW < 2 ? RBW : 2) * 12 : 0);
+  return mfma_lds_bytes<N, T, MIX>() <= 160 * 1024 && acc <= 144;
 }
 
 // Raw buffer loads: a 128-bit resource (base, size) in SGPRs plus a 32-bit
@@ -211,13 +241,15 @@ __device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t vof
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
-// State shared by the two waves of a workgroup.
-template <int N, typename T, bool HALF = false, bool MAT = false>
+// State shared by the waves of a workgroup.
+template <int N, typename T, bool HALF = false, bool MAT = false, bool SPLIT = false>
 struct MfmaTile {
   using S = MfmaShape<N>;
   static constexpr bool kHalf = HALF;
   static constexpr int kFaceRec = MAT ? 8 : 4;
-  T su[S::tile(HALF)];                // fields [c][j][e], then fluxes [c][m][e], then output
+  // fields [c][j][e], then fluxes [c][m][e], then output [c][e][i]; the split
+  // forms hold rows [c][e] of records (SplitShape) in place of the first two
+  alignas(16) T su[SPLIT ? SplitShape<N>::TILE : S::tile(HALF)];
   int16_t fmask[S::NF];
   alignas(16) uint8_t nbr[(4 * 24 * S::Nfp + 15) / 16 * 16];
   int32_t code[16 * 4];               // face codes of the tile's elements
@@ -399,176 +431,229 @@ __device__ __attribute__((always_inline)) inline void mfma_wave(const RhsArgs& a
 // ---------------------------------------------------------------------------
 // Split-precision contraction on 16-bit matrix cores.
 //
-// Same product as mfma_wave, with 16x16x16 MFMAs in BF16 or FP16 and FP32
+// Same operator as mfma_wave, on 16x16x32 MFMAs in BF16 or FP16 with FP32
 // accumulation.  Both operands are split into a 16-bit head and a 16-bit
-// tail, a = a_hi + a_lo with a_hi = round(a), a_lo = round(a - a_hi); the
-// operator's split is done once on the host, the fields' and fluxes' split in
-// registers.  NPROD selects the products accumulated: 1: a_hi b_hi,
-// 2: + a_lo b_hi, 3: + a_hi b_lo (the a_lo b_lo term is below FP32 rounding).
-// Depth: the volume columns (3 directions x Np4) padded to 16, then the LIFT
-// columns padded to 16; a lane's 4 consecutive depth entries always lie in
-// one direction block or in the LIFT block.
+// tail, a = a_hi + a_lo with a_hi = round(a), a_lo = round(a - a_hi): the
+// operator once on the host, the fields and the fluxes once per tile in LDS.
+// NPROD selects the products accumulated: 1: a_hi b_hi, 2: + a_lo b_hi,
+// 3: + a_hi b_lo (the a_lo b_lo term is below FP32 rounding).
+//
+// The metric is applied after the contraction: per direction d the wave
+// forms Y = D_d V for the three components of its source field V (H for the
+// E equations, -E for the H equations) and folds m_d x Y into its output, so
+// the operand of the volume MFMAs is the field itself -- split once per tile
+// and shared by both roles -- instead of m_d x V split again per direction and
+// role.  Depth: 32 nodes of one direction per step (each direction padded to
+// a multiple of 32), then the lift's face nodes, padded to 32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// 16x16x32 MFMA: lane l supplies A[l % 16][8 (l / 16) + v] and
+// B[8 (l / 16) + v][l % 16], v = 0..7; accumulator register r of lane l holds
+// D[4 (l / 16) + r][l % 16] (checked on gfx950 against a host product).
 template <typename H16>
-struct Mfma16x16;
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+struct Mfma32;
 template <>
-struct Mfma16x16<__bf16> {
-  using v4 = bf16x4;
-  __device__ static inline f32x4 mac(v4 a, v4 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+struct Mfma32<__bf16> {
+  using v8 = bf16x8;
+  __device__ static inline f32x4 mac(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
 };
 template <>
-struct Mfma16x16<_Float16> {
-  using v4 = f16x4;
-  __device__ static inline f32x4 mac(v4 a, v4 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+struct Mfma32<_Float16> {
+  using v8 = f16x8;
+  __device__ static inline f32x4 mac(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
 };
 
-template <int N>
-struct MixedShape {
-  using S = MfmaShape<N>;
-  static constexpr int KV = ((3 * S::Np4 + 15) / 16) * 16;  // volume depth, padded
-  static constexpr int KL = ((S::NF + 15) / 16) * 16;       // LIFT depth, padded
-  static constexpr int SV = KV / 16, SL = KL / 16, ST = SV + SL;
-  // fragments: [row block][depth step][lane] x (4 heads, 4 tails) of 16 bits
-  static constexpr int frag_bytes = S::RB * ST * 64 * 16;
-};
-
 template <typename H16>
-__device__ inline void split4(const float (&x)[4], typename Mfma16x16<H16>::v4& hi,
-                              typename Mfma16x16<H16>::v4& lo) {
+__device__ inline void split8(const float (&x)[8], typename Mfma32<H16>::v8& hi, typename Mfma32<H16>::v8& lo) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
+  for (int v = 0; v < 8; ++v) {
     const H16 h = static_cast<H16>(x[v]);
     hi[v] = h;
     lo[v] = static_cast<H16>(x[v] - static_cast<float>(h));
   }
 }
 
-template <int N, typename H16, int NPROD, int H, bool IL, int NFI, int RBW, bool PALT, typename Gather,
-          typename FluxStep, typename FluxStore>
-__device__ __attribute__((always_inline)) inline void mixed_wave(const RhsArgs& a, MfmaTile<N, float>& t, const float (&mr)[9], int lane, int rb0,
-                                  f32x4 (&acc)[RBW][3], Gather&& gather, FluxStep&& flux_step,
-                                  FluxStore&& flux_store) {
-  using S = MfmaShape<N>;
-  using X = MixedShape<N>;
-  using MM = Mfma16x16<H16>;
-  using v4 = typename MM::v4;
-  constexpr int Np4 = S::Np4, NF = S::NF, RB = RBW, TS = S::TS, TQ = S::TQ;
-  constexpr int SV = X::SV, SL = X::SL, ST = X::ST;
-  const int e = lane & 15, q = lane >> 4;
-  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag16, uint32_t(X::frag_bytes));
+// Splits the FP32 records of ROWS rows of stride RS (J records each) at src
+// into head/tail records at dst (dst == src: in place); run by NT lanes.
+template <typename H16, int ROWS, int J, int RS, int NT>
+__device__ __attribute__((always_inline)) inline void split_records(const float* src, float* dst, int tid) {
+  using v8 = typename Mfma32<H16>::v8;
+  constexpr int n = ROWS * J;
 #pragma unroll
-  for (int ib = 0; ib < RB; ++ib)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[ib][c] = f32x4{0, 0, 0, 0};
-
-  // A fragments (head, tail) prefetched kPre steps ahead (PALT: one step).
-  constexpr int kPre = PALT ? 1 : 2;
-  using FS = FluxSchedule<SV, NFI, kPre>;
-  auto frag_of = [&](int step, int ib, v4& hi, v4& lo) {
-    const uint32_t off = uint32_t((((rb0 + ib) * ST + step) * 64 + lane) * 16);
-    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 0, 0);
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    hi = __builtin_bit_cast(v4, u32x2{w[0], w[1]});
-    lo = __builtin_bit_cast(v4, u32x2{w[2], w[3]});
-  };
-  v4 Ahi[kPre + 1][RB], Alo[kPre + 1][RB];
-#pragma unroll
-  for (int s = 0; s < kPre; ++s)
-#pragma unroll
-    for (int ib = 0; ib < RB; ++ib) frag_of(s, ib, Ahi[s][ib], Alo[s][ib]);
-
-  auto mma = [&](int step, const v4 (&bh)[3], const v4 (&bl)[3]) {
-    const int slot = step % (kPre + 1);
-#pragma unroll
-    for (int ib = 0; ib < RB; ++ib)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        acc[ib][c] = MM::mac(Ahi[slot][ib], bh[c], acc[ib][c]);
-        if constexpr (NPROD >= 2) acc[ib][c] = MM::mac(Alo[slot][ib], bh[c], acc[ib][c]);
-        if constexpr (NPROD >= 3) acc[ib][c] = MM::mac(Ahi[slot][ib], bl[c], acc[ib][c]);
-      }
-  };
-
-  // Volume: depth entries kappa = 16 s + 4 q + v, direction d = kappa / Np4,
-  // node j = kappa % Np4; operand X_d = m_d x V with V = H (H = 0) or -E.
-  constexpr int vb = H ? 0 : 3;
-  const float vs = H ? -1.f : 1.f;
-#pragma unroll
-  for (int s = 0; s < SV; ++s) {
-    if (s + kPre < ST) {
-#pragma unroll
-      for (int ib = 0; ib < RB; ++ib) frag_of(s + kPre, ib, Ahi[(s + kPre) % (kPre + 1)][ib], Alo[(s + kPre) % (kPre + 1)][ib]);
-    }
-    if constexpr (IL) {
-      if (s == 0) gather();
-    }
-    const int kap = 16 * s + 4 * q;
-    float xv[3][4];
-    if (kap < 3 * Np4) {
-      const int d = kap / Np4, j = kap - d * Np4;
-      const float mx = mr[3 * d], my = mr[3 * d + 1], mz = mr[3 * d + 2];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float v0 = vs * t.su[((vb + 0) * Np4 + j + v) * TS + e];
-        const float v1 = vs * t.su[((vb + 1) * Np4 + j + v) * TS + e];
-        const float v2 = vs * t.su[((vb + 2) * Np4 + j + v) * TS + e];
-        xv[0][v] = my * v2 - mz * v1;
-        xv[1][v] = mz * v0 - mx * v2;
-        xv[2][v] = mx * v1 - my * v0;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) xv[c][v] = 0.f;
-    }
-    v4 bh[3], bl[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) split4<H16>(xv[c], bh[c], bl[c]);
-    mma(s, bh, bl);
-    if constexpr (IL) {
-#pragma unroll
-      for (int fi = 0; fi < NFI; ++fi)
-        if (FS::at(fi) == s) flux_step(fi);
+  for (int it = 0; it < (n + NT - 1) / NT; ++it) {
+    const int r = tid + NT * it;
+    if (r < n) {
+      const int row = r / J, j8 = r - row * J;
+      const int o = row * RS + 8 * j8;
+      const f32x4 a = *reinterpret_cast<const f32x4*>(src + o);
+      const f32x4 b = *reinterpret_cast<const f32x4*>(src + o + 4);
+      const float x[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+      v8 hi, lo;
+      split8<H16>(x, hi, lo);
+      *reinterpret_cast<v8*>(dst + o) = hi;
+      *reinterpret_cast<v8*>(dst + o + 4) = lo;
     }
   }
-  if constexpr (IL) {
+}
+
+// Contraction of one wave of a split form: H as in mfma_wave; the wave
+// produces row blocks rb0 .. rb0 + RBW - 1, G at a time (Y holds G blocks).
+template <int N, typename H16, int NPROD, int H, int NFI, int RBW, bool PALT, typename Tile, typename Gather,
+          typename FluxStep, typename FluxPut, typename FluxStore>
+__device__ __attribute__((always_inline)) inline void split_wave(const RhsArgs& a, Tile& t, const float (&mr)[9],
+                                                                 int lane, int rb0, f32x4 (&out)[RBW][3],
+                                                                 Gather&& gather, FluxStep&& flux_step,
+                                                                 FluxPut&& flux_put, FluxStore&& flux_store) {
+  using X = SplitShape<N>;
+  using MM = Mfma32<H16>;
+  using v8 = typename MM::v8;
+  constexpr int KV = X::KV, KL = X::KL, ST = X::ST, J8 = X::J8, J8F = X::J8F, RSV = X::RSV, RSF = X::RSF;
+  constexpr int G = RBW < 2 ? RBW : 2;      // row blocks per pass
+  constexpr int NG = (RBW + G - 1) / G;     // passes
+  constexpr int NVS = NG * 3 * KV;          // volume steps of this wave (pass, direction, depth)
+  constexpr int NS = NVS + NG * KL;         // then the lift steps (pass, depth)
+  const int e = lane & 15, q = lane >> 4;
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag16, uint32_t(X::frag_bytes));
+
+  // Operator fragments (head, tail) of step s for block gi of its pass,
+  // prefetched kPre steps ahead: two with up to four row blocks per wave,
+  // one beyond, where the registers are short (PALT: the other depth).  The
+  // lift's first fragments are issued once the fluxes are in registers and
+  // the gathered traces are dead, so that none is held through the flux phase.
+  constexpr int kPreD = RBW <= 4 ? 2 : 1;
+  constexpr int kPre = PALT ? 3 - kPreD : kPreD;
+  auto frag_of = [&](int s, int gi, v8& hi, v8& lo) {
+    const int g = s < NVS ? s / (3 * KV) : (s - NVS) / KL;
+    const int st = s < NVS ? s % (3 * KV) : 3 * KV + (s - NVS) % KL;
+    const int ib = rb0 + g * G + gi;
+    const uint32_t off = uint32_t(((ib * ST + st) * 2 * 64 + lane) * 16);
+    hi = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 0, 0));
+    if constexpr (NPROD >= 2)
+      lo = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 64 * 16, 0));
+  };
+  v8 Ahi[kPre + 1][G], Alo[kPre + 1][G];
+  auto fetch = [&](int s) {
+    if (s < NS) {
+      const int g = s < NVS ? s / (3 * KV) : (s - NVS) / KL;
 #pragma unroll
-    for (int fi = 0; fi < NFI; ++fi)
-      if (FS::at(fi) >= SV) flux_step(fi);
+      for (int gi = 0; gi < G; ++gi)
+        if (g * G + gi < RBW) frag_of(s, gi, Ahi[s % (kPre + 1)][gi], Alo[s % (kPre + 1)][gi]);
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < kPre; ++s) fetch(s);
+
+  // B operands of one step: the record of each component for this lane's
+  // element and depth group (records past the row's end are clamped: the
+  // operator columns there are zero, and the clamped record is finite).
+  auto b_of = [&](const float* row0, int rs, int rec, v8 (&bh)[3], v8 (&bl)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float* p = row0 + (c * 16 + e) * rs + 8 * rec;
+      bh[c] = *reinterpret_cast<const v8*>(p);
+      if constexpr (NPROD >= 3) bl[c] = *reinterpret_cast<const v8*>(p + 4);
+    }
+  };
+  auto mma = [&](int s, int g, const v8 (&bh)[3], const v8 (&bl)[3], f32x4 (&acc)[G][3], bool first) {
+    const int slot = s % (kPre + 1);
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (g * G + gi >= RBW) continue;
+        f32x4 y = MM::mac(Ahi[slot][gi], bh[c], first ? f32x4{0, 0, 0, 0} : acc[gi][c]);
+        if constexpr (NPROD >= 2) y = MM::mac(Alo[slot][gi], bh[c], y);
+        if constexpr (NPROD >= 3) y = MM::mac(Ahi[slot][gi], bl[c], y);
+        acc[gi][c] = y;
+      }
+  };
+
+  // Volume: Y = D_d V per pass and direction, then out += m_d x Y with the
+  // role's sign (V = H for the E equations, -E for the H equations).
+  constexpr int vb = H ? 0 : 3;
+  const float vs = H ? -1.f : 1.f;
+  const float* fv = t.su + X::SPLIT + vb * 16 * RSV;
+  f32x4 Y[G][3];
+#pragma unroll
+  for (int s = 0; s < NVS; ++s) {
+    if (s + kPre < NVS) fetch(s + kPre);
+    const int g = s / (3 * KV), d = (s / KV) % 3, ks = s % KV;
+    const int rec = 4 * ks + q < J8 ? 4 * ks + q : J8 - 1;
+    // Each direction reads its operands afresh: shared with the other
+    // directions they would keep all three partial products live at once.
+    if (ks == 0 && s > 0) asm volatile("" ::: "memory");
+    v8 bh[3], bl[3];
+    b_of(fv, RSV, rec, bh, bl);
+    mma(s, g, bh, bl, Y, ks == 0);
+    if (ks == KV - 1) {
+      const float mx = vs * mr[3 * d], my = vs * mr[3 * d + 1], mz = vs * mr[3 * d + 2];
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) {
+        const int ib = g * G + gi;
+        if (ib >= RBW) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float c0 = my * Y[gi][2][r] - mz * Y[gi][1][r];
+          const float c1 = mz * Y[gi][0][r] - mx * Y[gi][2][r];
+          const float c2 = mx * Y[gi][1][r] - my * Y[gi][0][r];
+          out[ib][0][r] = d == 0 ? c0 : out[ib][0][r] + c0;
+          out[ib][1][r] = d == 0 ? c1 : out[ib][1][r] + c1;
+          out[ib][2][r] = d == 0 ? c2 : out[ib][2][r] + c2;
+        }
+        // The fold completes here, before the next direction's operands are
+        // read, so that only one direction's partial products are live.
+#pragma unroll
+        for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(out[ib][c]));
+      }
+    }
+  }
+  if constexpr (X::INPLACE) {
+    // The field records are the tile's only copy of the fields, and the
+    // flux rows replace them: once every wave is done with them, the fluxes
+    // go to LDS as they are computed, FCH iterations at a time, the traces of
+    // the next FCH in flight meanwhile.
+    constexpr int FCH = 2;
+    gather(0, FCH);
+    __syncthreads();
+#pragma unroll
+    for (int c0 = 0; c0 < NFI; c0 += FCH) {
+      if (c0 + FCH < NFI) gather(c0 + FCH, c0 + 2 * FCH);
+#pragma unroll
+      for (int fi = c0; fi < c0 + FCH && fi < NFI; ++fi) {
+        flux_step(fi);
+        flux_put(fi);
+      }
+    }
+#pragma unroll
+    for (int s = NVS; s < NVS + kPre; ++s) fetch(s);
+    flux_store(-2);
   } else {
     gather();
 #pragma unroll
     for (int fi = 0; fi < NFI; ++fi) flux_step(fi);
+#pragma unroll
+    for (int s = NVS; s < NVS + kPre; ++s) fetch(s);
+    flux_store(-1);
   }
 
-  // Lifting: fluxes from the LDS flux tile written by the workgroup.
-  flux_store(-1);
+  // Lifting: the fluxes' head/tail records written by the workgroup.
   __syncthreads();
   constexpr int cb = H ? 3 : 0;
+  const float* fq = t.su + cb * 16 * RSF;
 #pragma unroll
-  for (int s = 0; s < SL; ++s) {
-    const int step = SV + s;
-    if (step + kPre < ST) {
-#pragma unroll
-      for (int ib = 0; ib < RB; ++ib)
-        frag_of(step + kPre, ib, Ahi[(step + kPre) % (kPre + 1)][ib], Alo[(step + kPre) % (kPre + 1)][ib]);
-    }
-    const int m = 16 * s + 4 * q;
-    float fv[3][4];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) fv[c][v] = (m + v < NF) ? t.su[((cb + c) * NF + m + v) * TQ + e] : 0.f;
-    v4 bh[3], bl[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) split4<H16>(fv[c], bh[c], bl[c]);
-    mma(step, bh, bl);
+  for (int s = NVS; s < NS; ++s) {
+    fetch(s + kPre);
+    const int g = (s - NVS) / KL, ls = (s - NVS) % KL;
+    const int rec = 4 * ls + q < J8F ? 4 * ls + q : J8F - 1;
+    v8 bh[3], bl[3];
+    b_of(fq, RSF, rec, bh, bl);
+    auto& acc = *reinterpret_cast<f32x4(*)[G][3]>(&out[g * G]);
+    mma(s, g, bh, bl, acc, false);
   }
 }
 
@@ -576,10 +661,10 @@ __device__ __attribute__((always_inline)) inline void mixed_wave(const RhsArgs& 
 // FluxSchedule): the neighbour traces, then the fluxes computed from them
 // (6 scalars per flux iteration), stay in registers through the volume loop.
 // Measured on MI355X it pays in FP64 (7% at N = 3, the order where the
-// registers allow it); in FP32 and the split precisions it costs a wave per
-// SIMD and gains nothing: the FP32 matrix and vector pipes never co-issue
-// (SQ_VALU_MFMA_COEXEC_CYCLES reads 0), and the split forms are bound by the
-// vector ALU already.
+// registers allow it); in FP32 it costs a wave per SIMD and gains nothing
+// (the FP32 matrix and vector pipes never co-issue: SQ_VALU_MFMA_COEXEC_CYCLES
+// reads 0).  The split forms do not interleave: their fluxes go through LDS
+// rows that replace the field tile.
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr bool flux_interleaved() {
   constexpr int iters = (16 * MfmaShape<N>::NF + 127) / 128;
@@ -600,8 +685,8 @@ constexpr bool lift_split() {
 // Workgroup = two or four waves sharing one tile of 16 elements; wave role
 // h = 0 produces the E equations, h = 1 the H equations (see mfma_wave).
 // MIX = 0: contraction in T on 16x16x4 MFMAs; MIX = 1..3: T = float with the
-// contraction split in BF16 (NPROD = MIX); MIX = 4..6: split in FP16
-// (NPROD = MIX - 3).
+// contraction split in BF16 (NPROD = MIX) on 16x16x32 MFMAs (split_wave);
+// MIX = 4..6: split in FP16 (NPROD = MIX - 3).
 //
 // MAT: per-element eps and mu (material record, see kMatStride): the metric
 // of the volume operand is scaled by 1 / eps (E role) or 1 / mu (H role), and
@@ -620,8 +705,14 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   constexpr int NT = 64 * WPT;        // lanes per tile
   constexpr int RBW = row_blocks_first<N, T, MIX, CFG>();    // row blocks of a role's first wave
   constexpr int RBW1 = row_blocks_second<N, T, MIX, CFG>();  // and of its second (four waves per tile)
-  __shared__ MfmaTile<N, T, LIFT_HALF, MAT> t;
-  constexpr int FREC = MfmaTile<N, T, LIFT_HALF, MAT>::kFaceRec;
+  // Split forms: the 16-bit type, the products, the LDS rows (SplitShape).
+  constexpr bool SPL = MIX != 0;
+  using H16 = typename std::conditional<(MIX <= 3), __bf16, _Float16>::type;
+  constexpr int NPROD = MIX <= 3 ? MIX : MIX - 3;
+  using X = SplitShape<N>;
+  constexpr bool OWNG = SPL && X::INPLACE;  // own traces of the flux from global memory
+  __shared__ MfmaTile<N, T, LIFT_HALF, MAT, SPL> t;
+  constexpr int FREC = MfmaTile<N, T, LIFT_HALF, MAT, SPL>::kFaceRec;
 
   const int64_t fs = a.fs;
   const int tid = threadIdx.x;
@@ -733,19 +824,42 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     const int i = tid + NT * it;
     if (i < kNbrVec) reinterpret_cast<uint4*>(t.nbr)[i] = nbv[it];
   }
+  if constexpr (SPL) {
+    // FP32 rows [c][e] (records of 8 nodes, zero past Np), then their
+    // head/tail records in the split region (or in place).
 #pragma unroll
-  for (int it = 0; it < kLoadIters; ++it) {
-    const int idx = tid + NT * it;
-    const int ee = idx / Np, j = idx - ee * Np;
-    if (idx < 16 * Np) {
+    for (int it = 0; it < kLoadIters; ++it) {
+      const int idx = tid + NT * it;
+      const int ee = idx / Np, j = idx - ee * Np;
+      if (idx < 16 * Np) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) t.su[(c * Np4 + j) * TS + ee] = tv[it][c];
+        for (int c = 0; c < 6; ++c) t.su[(c * 16 + ee) * X::RSV + j] = tv[it][c];
+      }
     }
-  }
-  if constexpr (Np4 > Np) {
-    for (int idx = tid; idx < 6 * (Np4 - Np) * 16; idx += NT) {
-      const int c = idx / ((Np4 - Np) * 16), r = idx - c * ((Np4 - Np) * 16);
-      t.su[(c * Np4 + Np + r / 16) * TS + (r & 15)] = T(0);
+    constexpr int pad = 8 * X::J8 - Np;
+    if constexpr (pad > 0) {
+      for (int idx = tid; idx < 96 * pad; idx += NT) {
+        const int row = idx / pad;
+        t.su[row * X::RSV + Np + (idx - row * pad)] = T(0);
+      }
+    }
+    __syncthreads();
+    split_records<H16, 96, X::J8, X::RSV, NT>(t.su, t.su + X::SPLIT, tid);
+  } else {
+#pragma unroll
+    for (int it = 0; it < kLoadIters; ++it) {
+      const int idx = tid + NT * it;
+      const int ee = idx / Np, j = idx - ee * Np;
+      if (idx < 16 * Np) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t.su[(c * Np4 + j) * TS + ee] = tv[it][c];
+      }
+    }
+    if constexpr (Np4 > Np) {
+      for (int idx = tid; idx < 6 * (Np4 - Np) * 16; idx += NT) {
+        const int c = idx / ((Np4 - Np) * 16), r = idx - c * ((Np4 - Np) * 16);
+        t.su[(c * Np4 + Np + r / 16) * TS + (r & 15)] = T(0);
+      }
     }
   }
   __syncthreads();
@@ -756,14 +870,31 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // the field tile, which is then overwritten by the fluxes [c][m][e].
   constexpr int kPairs = 16 * NF;
   constexpr int kFluxIters = (kPairs + NT - 1) / NT;
+  // Pair pr of the tile: face-node-fastest, so that a gather instruction's
+  // lanes walk the faces of few elements and touch few cache lines of their
+  // neighbours (measured on MI355X: a fifth less time for the split forms at
+  // N = 5); element-fastest with the split lift, whose halves are runs of
+  // flux iterations over face-node rows.
+  auto pair_of = [&](int pr, int& ee, int& m) {
+    if constexpr (!LIFT_HALF) {
+      ee = pr / NF;
+      m = pr - ee * NF;
+    } else {
+      ee = pr & 15;
+      m = pr >> 4;
+    }
+  };
   const T alpha = T(a.alpha);
   T gx[kFluxIters][6];
+  T ox[OWNG ? kFluxIters : 1][6];
   T fl[kFluxIters][6];
-  auto gather = [&]() {
+  auto gather = [&](int it0 = 0, int it1 = 1 << 20) {
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
+      if (it < it0 || it >= it1) continue;
       const int pr = tid + NT * it;
-      const int ee = pr & 15, m = pr >> 4;
+      int ee, m;
+      pair_of(pr, ee, m);
       const int f = m / Nfp, jj = m - f * Nfp;
       const int32_t cf = (pr < kPairs) ? t.code[4 * ee + f] : -1;
       // interior: neighbour node; boundary: own node (mirror applied below); dead: zero
@@ -773,11 +904,23 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
                               : (k0 + ee) * Np + t.fmask[m]) * sz;
 #pragma unroll
       for (int c = 0; c < 6; ++c) gx[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
+      if constexpr (OWNG) {
+        const uint32_t oo = (pr < kPairs && ee < ne) ? uint32_t((k0 + ee) * Np + t.fmask[m]) * sz : kOob;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ox[it][c] = buf_load<T>(ru, oo, uint32_t(c * fs) * sz);
+      }
     }
+  };
+  // Own trace of component c at node own of element ee.
+  auto own_at = [&](int it, int c, int ee, int own) -> T {
+    if constexpr (OWNG) return ox[it][c];
+    else if constexpr (SPL) return t.su[(c * 16 + ee) * X::RSV + own];
+    else return t.su[(c * Np4 + own) * TS + ee];
   };
   auto flux_step = [&](int it) {
     const int pr = tid + NT * it;
-    const int ee = pr & 15, m = pr >> 4;
+    int ee, m;
+    pair_of(pr, ee, m);
     if (pr < kPairs) {
       const int f = m / Nfp;
       const int own = t.fmask[m];
@@ -788,12 +931,12 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       {
         const T se = cd >= 0 ? T(1) : (cd == -1 ? T(-1) : (cd == -2 ? T(1) : T(0)));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) d[c] = t.su[(c * Np4 + own) * TS + ee] - se * gx[it][c];
+        for (int c = 0; c < 3; ++c) d[c] = own_at(it, c, ee, own) - se * gx[it][c];
       }
       {
         const T sh = cd >= -1 ? T(1) : (cd == -2 ? T(-1) : T(0));
 #pragma unroll
-        for (int c = 3; c < 6; ++c) d[c] = t.su[(c * Np4 + own) * TS + ee] - sh * gx[it][c];
+        for (int c = 3; c < 6; ++c) d[c] = own_at(it, c, ee, own) - sh * gx[it][c];
       }
       const T* fr = &t.face[FREC * (4 * ee + f)];
       const T nx = fr[0], ny = fr[1], nz = fr[2];
@@ -821,7 +964,39 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // iterations of the first / second half of face-node rows, rows
   // c HB + m - part HB.  Parts -1 and 0 first wait until every read of the
   // field tile is done, since the fluxes overwrite it.
+  // Split forms: flux iteration it into the FP32 rows [c][e] of face-node
+  // records.
+  auto flux_put = [&](int it) {
+    if constexpr (SPL) {
+      const int pr = tid + NT * it;
+      int ee, m;
+      pair_of(pr, ee, m);
+      if (pr < kPairs) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t.su[(c * 16 + ee) * X::RSF + m] = fl[it][c];
+      }
+    }
+  };
   auto flux_store = [&](int part) {
+    if constexpr (SPL) {
+      // The rows (part -1: after every read of the field tile is done; part
+      // -2: already put), zero past NF, then split in place.
+      if (part == -1) {
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kFluxIters; ++it) flux_put(it);
+      }
+      constexpr int pad = 8 * X::J8F - NF;
+      if constexpr (pad > 0) {
+        for (int idx = tid; idx < 96 * pad; idx += NT) {
+          const int row = idx / pad;
+          t.su[row * X::RSF + NF + (idx - row * pad)] = T(0);
+        }
+      }
+      __syncthreads();
+      split_records<H16, 96, X::J8F, X::RSF, NT>(t.su, t.su, tid);
+      return;
+    }
     constexpr int FR = LIFT_HALF ? S::HB : NF;
     if (part <= 0) __syncthreads();
     const int it0 = part == 1 ? S::HALF_ITERS : 0;
@@ -830,7 +1005,8 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
       const int pr = tid + NT * it;
-      const int ee = pr & 15, m = pr >> 4;
+      int ee, m;
+      pair_of(pr, ee, m);
       if (it >= it0 && it < it1 && pr < kPairs) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) t.su[(c * FR + m - base) * TQ + ee] = fl[it][c];
@@ -867,17 +1043,15 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         role(std::false_type{}, B0{});
     }
   } else {
-    using H16 = typename std::conditional<(MIX <= 3), __bf16, _Float16>::type;
-    constexpr int NPROD = MIX <= 3 ? MIX : MIX - 3;
     auto role = [&](auto blocks) {
       constexpr int NB = decltype(blocks)::value;
       auto& ac = reinterpret_cast<acc_t(&)[NB][3]>(acc);
       if (h == 0)
-        mixed_wave<N, H16, NPROD, 0, IL, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
-                                                               flux_store);
+        split_wave<N, H16, NPROD, 0, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
+                                                           flux_put, flux_store);
       else
-        mixed_wave<N, H16, NPROD, 1, IL, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
-                                                               flux_store);
+        split_wave<N, H16, NPROD, 1, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
+                                                           flux_put, flux_store);
     };
     if constexpr (ONE_COPY) {
       role(B0{});
@@ -1035,14 +1209,16 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
 // waves per workgroup over the 4 SIMDs, at most 8).
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int lds_waves_per_simd() {
-  constexpr size_t tile_bytes = sizeof(MfmaTile<N, T, lift_split<N, T, MIX, CFG>(), false>);
+  constexpr size_t tile_bytes = sizeof(MfmaTile<N, T, lift_split<N, T, MIX, CFG>(), false, (MIX != 0)>);
   constexpr int wg = int((160 * 1024) / tile_bytes);
   constexpr int w = wg * waves_per_tile<N, T, MIX, CFG>() / 4;
   return w > 8 ? 8 : (w < 1 ? 1 : w);
 }
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int min_waves_per_simd() {
-  constexpr int d = (sizeof(T) == 4 && ((MIX == 0 && N == 6) || (MIX == 2 && N == 4))) ? 3 : 1;
+  // split forms: two waves per SIMD where the LDS allows them
+  constexpr int ls = lds_waves_per_simd<N, T, MIX, CFG>();
+  constexpr int d = (sizeof(T) == 4 && MIX == 0 && N == 6) ? 3 : (MIX != 0 ? (ls < 2 ? ls : 2) : 1);
   return CFG == kCfgOccupancy ? lds_waves_per_simd<N, T, MIX, CFG>() : d;
 }
 
