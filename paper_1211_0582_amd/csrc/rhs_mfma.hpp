@@ -246,16 +246,16 @@ template <int N, typename T, bool HALF = false, bool MAT = false, bool SPLIT = f
 struct MfmaTile {
   using S = MfmaShape<N>;
   static constexpr bool kHalf = HALF;
-  static constexpr int kFaceRec = MAT ? 8 : 4;
   // fields [c][j][e], then fluxes [c][m][e], then output [c][e][i]; the split
   // forms hold rows [c][e] of records (SplitShape) in place of the first two
   alignas(16) T su[SPLIT ? SplitShape<N>::TILE : S::tile(HALF)];
+  // geometry records of the tile's elements (kGeoStride values each)
+  alignas(16) T geo[(16 * kGeoStride * sizeof(T) + 15) / 16 * 16 / sizeof(T)];
   int16_t fmask[S::NF];
   alignas(16) uint8_t nbr[(4 * 24 * S::Nfp + 15) / 16 * 16];
   int32_t code[16 * 4];               // face codes of the tile's elements
-  // per (element, face): nx, ny, nz, Fscale / 2 (vacuum), or
-  // nx, ny, nz, s_E, s_H, a_E, a_H of the material record
-  T face[16 * 4 * kFaceRec];
+  // per (element, face): s_E, s_H, a_E, a_H of the material record
+  T face[MAT ? 16 * 4 * 4 : 1];
 };
 
 // Where the flux work of a tile runs relative to the contraction.  Flux
@@ -513,7 +513,7 @@ __device__ __attribute__((always_inline)) inline void split_wave(const RhsArgs& 
   using MM = Mfma32<H16>;
   using v8 = typename MM::v8;
   constexpr int KV = X::KV, KL = X::KL, ST = X::ST, J8 = X::J8, J8F = X::J8F, RSV = X::RSV, RSF = X::RSF;
-  constexpr int G = RBW < 2 ? RBW : 2;      // row blocks per pass
+  constexpr int G = RBW < 2 || RBW > 4 ? 1 : 2;  // row blocks per pass
   constexpr int NG = (RBW + G - 1) / G;     // passes
   constexpr int NVS = NG * 3 * KV;          // volume steps of this wave (pass, direction, depth)
   constexpr int NS = NVS + NG * KL;         // then the lift steps (pass, depth)
@@ -712,7 +712,6 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   using X = SplitShape<N>;
   constexpr bool OWNG = SPL && X::INPLACE;  // own traces of the flux from global memory
   __shared__ MfmaTile<N, T, LIFT_HALF, MAT, SPL> t;
-  constexpr int FREC = MfmaTile<N, T, LIFT_HALF, MAT, SPL>::kFaceRec;
 
   const int64_t fs = a.fs;
   const int tid = threadIdx.x;
@@ -738,30 +737,33 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // Every global load of the prologue is issued before the first LDS write:
   // a write needs its data, and a load issued after such a wait (or in a
   // later branch) would add a full memory round trip to the prologue.
-  // Metric of this lane's element in registers.
-  T mr[9];
-  {
-    const uint32_t go = live ? uint32_t(ke * kGeoStride) * sz : kOob;
+  // Geometry records of the tile (metric, then per face the normal and
+  // Fscale): one contiguous block, loaded with 16-byte loads into LDS (past
+  // the last element they read zero).
+  constexpr int kGeoVec = (16 * kGeoStride * int(sz) + 15) / 16;
+  constexpr int kGeoIters = (kGeoVec + NT - 1) / NT;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 gv[kGeoIters];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) mr[i] = buf_load<T>(rg, go, i * sz);
+  for (int it = 0; it < kGeoIters; ++it) {
+    const int i = tid + NT * it;
+    const uint32_t go = i < kGeoVec ? uint32_t(k0 * kGeoStride) * sz + 16u * uint32_t(i) : kOob;
+    gv[it] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rg, (int)go, 0, 0));
   }
   // Material: the role's 1 / eps or 1 / mu, and the face scales and weights.
   T mscale = T(1);
   T fmr[4] = {T(0), T(0), T(0), T(0)};
   const __amdgpu_buffer_rsrc_t rmat = make_rsrc(a.mat, MAT ? uint32_t(a.K) * kMatStride * sz : 0u);
   if constexpr (MAT) mscale = buf_load<T>(rmat, live ? uint32_t(ke * kMatStride + h) * sz : kOob, 0);
-  // Face records and connectivity codes (lanes 0..63: 16 elements x 4 faces).
-  T fc[4];
+  // Connectivity codes and material face records (lanes 0..63: 16 elements
+  // x 4 faces).
   int32_t cf;
   {
     const int ee = (tid >> 2) & 15, f = tid & 3;
     const bool lv = tid < 64 && ee < ne;
-    const uint32_t go = lv ? uint32_t((k0 + ee) * kGeoStride + 9 + 4 * f) * sz : kOob;
     cf = __builtin_bit_cast(int32_t, __builtin_amdgcn_raw_buffer_load_b32(
                                          rc, lv ? uint32_t((k0 + ee) * 4 + f) * 4 : kOob, 0, 0));
     cf = lv ? cf : -1;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) fc[i] = buf_load<T>(rg, go, i * sz);
     if constexpr (MAT) {
       const uint32_t mo = lv ? uint32_t((k0 + ee) * kMatStride + 2 + 4 * f) * sz : kOob;
 #pragma unroll
@@ -797,22 +799,18 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     for (int c = 0; c < 6; ++c) tv[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
   }
 
-  // LDS: face records, codes, tables, then the fields [c][j][e].
+  // LDS: geometry, codes, material face records, tables, then the fields.
+#pragma unroll
+  for (int it = 0; it < kGeoIters; ++it) {
+    const int i = tid + NT * it;
+    if (i < kGeoVec) reinterpret_cast<u32x4*>(t.geo)[i] = gv[it];
+  }
   if (tid < 64) {
     t.code[tid] = cf;
-    t.face[FREC * tid + 0] = fc[0];
-    t.face[FREC * tid + 1] = fc[1];
-    t.face[FREC * tid + 2] = fc[2];
     if constexpr (MAT) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) t.face[FREC * tid + 3 + i] = fmr[i];
-    } else {
-      t.face[FREC * tid + 3] = T(0.5) * fc[3];
+      for (int i = 0; i < 4; ++i) t.face[4 * tid + i] = fmr[i];
     }
-  }
-  if constexpr (MAT) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) mr[i] *= mscale;
   }
 #pragma unroll
   for (int it = 0; it < kFmaskIters; ++it) {
@@ -863,6 +861,14 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     }
   }
   __syncthreads();
+  // Metric of this lane's element, with a material the role's 1 / eps or 1 / mu.
+  T mr[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) mr[i] = t.geo[e * kGeoStride + i];
+  if constexpr (MAT) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) mr[i] *= mscale;
+  }
 
   // Flux phase, run by all lanes of the tile between the volume and the lift phases:
   // one lane per (element, face node) pair, each flux evaluated once.  All
@@ -938,16 +944,17 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
 #pragma unroll
         for (int c = 3; c < 6; ++c) d[c] = own_at(it, c, ee, own) - sh * gx[it][c];
       }
-      const T* fr = &t.face[FREC * (4 * ee + f)];
-      const T nx = fr[0], ny = fr[1], nz = fr[2];
+      const T* gr = &t.geo[ee * kGeoStride + 9 + 4 * f];
+      const T nx = gr[0], ny = gr[1], nz = gr[2];
       T scE, scH, aE, aH;
       if constexpr (MAT) {
-        scE = fr[3];
-        scH = fr[4];
-        aE = fr[5];
-        aH = fr[6];
+        const T* fr = &t.face[4 * (4 * ee + f)];
+        scE = fr[0];
+        scH = fr[1];
+        aE = fr[2];
+        aH = fr[3];
       } else {
-        scE = scH = fr[3];
+        scE = scH = T(0.5) * gr[3];
         aE = aH = alpha;
       }
       const T ndE = nx * d[0] + ny * d[1] + nz * d[2];
