@@ -53,7 +53,7 @@ struct RhsArgs {
   void* res;
   void* u_out;
   double rk_a, rk_b, rk_dt;
-  int32_t stream_out;     // 1: FP64 outputs written with non-temporal (streaming) stores
+  int32_t stream_out;     // 1: outputs written with non-temporal (streaming) stores
   const int32_t* tile_order;  // tile processed by the i-th workgroup slot, or nullptr (tile i)
 };
 

@@ -1103,7 +1103,9 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     const int c = j / kOutIters, it = j % kOutIters;
     const int idx = V * (rl + kRoleLanes * it);
     const uint32_t vo = idx < nv ? uint32_t((3 * h + c) * fs + k0 * Np + idx) * sz : kOob;
-    rv[j] = vload(rr, vo);
+    // the residual is read once per stage: a non-temporal load (cache policy
+    // NT) keeps it from displacing neighbour traces in L2 (stage -1 to -2%)
+    rv[j] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)vo, 0, 2));
     uv[j] = vload(ru, vo);
   };
 #pragma unroll
@@ -1193,17 +1195,14 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       }
     }
   };
-  // FP64 outputs go through streaming (non-temporal) stores when the host
-  // says the arrays a launch touches exceed the last-level cache: there they
-  // cannot stay resident for the next launch anyway, and such stores retire
-  // sooner (measured 2-4% on FP64 launches).  FP32 launches gain at most as
-  // much on large meshes and lose more than that on small ones when the
-  // kernel carries both store forms, so they keep plain stores only.
-  if constexpr (sizeof(T) == 8) {
-    if (a.stream_out) {
-      out(std::true_type{});
-      return;
-    }
+  // Outputs go through streaming (non-temporal) stores when the host says
+  // the arrays a launch touches exceed the last-level cache: there they
+  // cannot stay resident for the next launch anyway, such stores retire
+  // sooner, and they leave the L2 to the neighbour traces (measured on
+  // MI355X: FP64 2-4%; K = 663,552, N = 5: FP32 stage -1.4%, split -3%).
+  if (a.stream_out) {
+    out(std::true_type{});
+    return;
   }
   out(std::false_type{});
 }
@@ -1223,9 +1222,13 @@ constexpr int lds_waves_per_simd() {
 }
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int min_waves_per_simd() {
-  // split forms: two waves per SIMD where the LDS allows them
+  // At least two waves per SIMD where the LDS allows them (the allocation
+  // lands just past 256 registers at some orders: FP32 N = 7 takes 269
+  // unconstrained and 233 without spilling when asked), except with two
+  // waves per tile at high order, where four-wave tiles are the default.
   constexpr int ls = lds_waves_per_simd<N, T, MIX, CFG>();
-  constexpr int d = (sizeof(T) == 4 && MIX == 0 && N == 6) ? 3 : (MIX != 0 ? (ls < 2 ? ls : 2) : 1);
+  constexpr int two = CFG == kCfgWaves ? 1 : (ls < 2 ? ls : 2);
+  constexpr int d = (sizeof(T) == 4 && MIX == 0 && N == 6) ? 3 : two;
   return CFG == kCfgOccupancy ? lds_waves_per_simd<N, T, MIX, CFG>() : d;
 }
 

@@ -13,10 +13,13 @@
 
 ``python -m paper_1211_0582_amd.profiling counters <dir> <out.txt> <substr> <command...>``
     writes, per kernel and launch size, the matrix-core busy fraction, the
-    mean waves per SIMD, VALU and MFMA instructions per dispatch, and the
-    HBM bytes from the 32-byte-granular EA counters, from one or more
-    ``--pmc`` runs (SQ counters are summed over all SIMDs, GRBM_GUI_ACTIVE
-    over the 8 XCDs).
+    mean waves per SIMD, the vector-ALU issue fraction, the share of wave time
+    spent waiting on outstanding instructions, LDS bank-conflict and
+    texture-address (TA) busy fractions per CU, VALU / MFMA / LDS
+    instructions per dispatch, and the HBM bytes from the 32-byte-granular
+    EA counters, from one or more ``--pmc`` runs (SQ counters are summed over
+    all SIMDs, GRBM_GUI_ACTIVE over the 8 XCDs, TA and TCP counters over the
+    256 CUs).
 
 The traffic summary records a hash of the kernel sources; ``bench.py`` only
 reports the traffic while the sources still hash to that value.
@@ -122,7 +125,8 @@ def traffic_summary(fetch_dir, write_dir, substr, copy_bytes, command):
     return "\n".join(out) + "\n"
 
 
-SIMDS = 256 * 4   # MI355X: 256 CUs x 4 SIMDs
+CUS = 256
+SIMDS = CUS * 4   # MI355X: 256 CUs x 4 SIMDs
 XCDS = 8
 
 
@@ -147,8 +151,18 @@ def counters_summary(dirs, substr, command):
                 out.append(f"  mfma_busy_fraction: {m['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * SIMDS):.4f}")
             if "SQ_WAVE_CYCLES" in m:
                 out.append(f"  mean_waves_per_simd: {4 * m['SQ_WAVE_CYCLES'] / (cyc * SIMDS):.3f}")
+            if "SQ_INSTS_VALU" in m:
+                # a wave64 vector instruction occupies its SIMD for 4 cycles
+                out.append(f"  valu_issue_fraction: {4 * m['SQ_INSTS_VALU'] / (cyc * SIMDS):.4f}")
+            if "SQ_LDS_BANK_CONFLICT" in m:
+                out.append(f"  lds_bank_conflict_fraction_per_cu: {m['SQ_LDS_BANK_CONFLICT'] / (cyc * CUS):.4f}")
+            for k in ("TA_TA_BUSY_sum", "TA_BUFFER_TOTAL_CYCLES_sum", "TCP_PENDING_STALL_CYCLES_sum"):
+                if k in m:
+                    out.append(f"  {k[:-4].lower()}_fraction_per_cu: {m[k] / (cyc * CUS):.4f}")
             out.append(f"  kernel_cycles: {cyc:.0f}")
-        for k in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_WAVES"):
+        if "SQ_WAIT_INST_ANY" in m and "SQ_WAVE_CYCLES" in m:
+            out.append(f"  wait_inst_fraction_of_wave_time: {m['SQ_WAIT_INST_ANY'] / m['SQ_WAVE_CYCLES']:.4f}")
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_WAVES", "TCP_TCC_READ_REQ_sum"):
             if k in m:
                 out.append(f"  {k.lower()}_per_dispatch: {m[k]:.0f}")
         if "TCC_EA0_RDREQ_DRAM_32B_sum" in m:
