@@ -99,8 +99,9 @@ struct MfmaShape {
   static constexpr int TS = 17, TQ = 17;
   static constexpr int frag_count = RB * KS * 64;
   // The LDS tile holds the fields [c][Np4][TS] first, then the fluxes
-  // [c][NF][TQ], then the output staging [c][16][Np].
-  static constexpr int FIELDS = 6 * Np4 * TS, FLUXES = 6 * NF * TQ, STAGE = 6 * 16 * Np;
+  // [c][NF][TQ], then the output staging [c][16][Np] and 4 discard slots per
+  // lane.
+  static constexpr int FIELDS = 6 * Np4 * TS, FLUXES = 6 * NF * TQ, STAGE = 6 * 16 * Np + 256;
   static constexpr int TILE = FIELDS > FLUXES ? (FIELDS > STAGE ? FIELDS : STAGE) : (FLUXES > STAGE ? FLUXES : STAGE);
   // Split lift: the fluxes go to LDS and are lifted in two halves of face
   // nodes, m < HB and m >= HB, through a region of 6 x HB rows.  The flux
@@ -136,7 +137,7 @@ struct SplitShape {
   static constexpr bool INPLACE = 2 * 96 * RSV * 4 > 80 * 1024;
   static constexpr int SPLIT = INPLACE ? 0 : 96 * RSV;  // offset of the split field records
   static constexpr int max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
-  static constexpr int TILE = max3(SPLIT + 96 * RSV, 96 * RSF, 96 * S::Np);
+  static constexpr int TILE = max3(SPLIT + 96 * RSV, 96 * RSF, S::STAGE);
   // operator fragments: [row block][step][head, tail][lane] x 16 bytes
   static constexpr int frag_bytes = S::RB * ST * 2 * 64 * 16;
 };
@@ -1112,6 +1113,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   for (int j = 0; j < kAhead; ++j) rk_load(j);
   __syncthreads();
   T* so = t.su + h * (3 * 16 * Np);
+  T* discard = t.su + 6 * 16 * Np + 4 * lane;
   const bool tail_wave = TAIL && rb0 + nb == RB;
 #pragma unroll
   for (int ib = 0; ib < RBW; ++ib)
@@ -1133,10 +1135,12 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         }
         continue;
       }
+      // Rows past Np go to a per-lane discard slot after the staging area:
+      // an address select instead of a branch per row.
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * (rb0 + ib) + M::row(q, r);
-        if (i < Np) so[(c * 16 + e) * Np + i] = acc[ib][c][r];
+        *(i < Np ? &so[(c * 16 + e) * Np + i] : discard + r) = acc[ib][c][r];
       }
     }
   __syncthreads();
@@ -1147,50 +1151,48 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     const int idx = V * (rl + kRoleLanes * it);
     return *reinterpret_cast<const VT*>(&so[c * 16 * Np + (idx < 16 * Np ? idx : 16 * Np - V)]);
   };
-  // Store of V values at p[idx..]: one 16-byte store, or per value at the
-  // end of a ragged tile.
-  auto put = [&](auto streaming, T* p, int idx, VT v) {
-    if (idx + V <= nv) {
-      if constexpr (decltype(streaming)::value)
-        __builtin_nontemporal_store(v, reinterpret_cast<VT*>(p + idx));
-      else
-        *reinterpret_cast<VT*>(p + idx) = v;
-    } else {
-#pragma unroll
-      for (int w = 0; w < V; ++w)
-        if (idx + w < nv) p[idx + w] = v[w];
-    }
+  // Stores go through one buffer resource per output field that covers just
+  // the field's K Np values: the 16-byte store that straddles the end of a
+  // ragged last tile loses its out-of-range dwords (the range check is per
+  // dword), so no store sits behind a per-value branch.  The role is
+  // wave-uniform, which makes the resources scalar.
+  const int hu = __builtin_amdgcn_readfirstlane(h);
+  typedef uint32_t w32x4 __attribute__((ext_vector_type(4)));
+  auto field_rsrc = [&](void* base, int c) {
+    return make_rsrc(static_cast<T*>(base) + (3 * hu + c) * fs, uint32_t(a.K) * Np * sz);
+  };
+  auto put = [&](auto streaming, __amdgpu_buffer_rsrc_t r, int idx, VT v) {
+    const uint32_t vo = idx < nv ? uint32_t(k0 * Np + idx) * sz : kOob;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(w32x4, v), r, (int)vo, 0,
+                                           decltype(streaming)::value ? 2 : 0);
   };
   auto out = [&](auto streaming) {
     if constexpr (!RK) {
-      T* __restrict__ rhs = static_cast<T*>(a.rhs);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         VT ov[kOutIters];
 #pragma unroll
         for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
-        T* base = rhs + (3 * h + c) * fs + k0 * Np;
+        const __amdgpu_buffer_rsrc_t ro = field_rsrc(a.rhs, c);
 #pragma unroll
-        for (int it = 0; it < kOutIters; ++it) put(streaming, base, V * (rl + kRoleLanes * it), ov[it]);
+        for (int it = 0; it < kOutIters; ++it) put(streaming, ro, V * (rl + kRoleLanes * it), ov[it]);
       }
     } else {
-      T* __restrict__ res = static_cast<T*>(a.res);
-      T* __restrict__ uo = static_cast<T*>(a.u_out);
       const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         VT ov[kOutIters];
 #pragma unroll
         for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
-        const int64_t g = (3 * h + c) * fs + k0 * Np;
+        const __amdgpu_buffer_rsrc_t rs = field_rsrc(a.res, c), rn = field_rsrc(a.u_out, c);
 #pragma unroll
         for (int it = 0; it < kOutIters; ++it) {
           const int j = c * kOutIters + it;
           if (j + kAhead < kItems) rk_load(j + kAhead);
           const VT r = ra * rv[j] + dt * ov[it];
           const int idx = V * (rl + kRoleLanes * it);
-          put(streaming, res + g, idx, r);
-          put(streaming, uo + g, idx, uv[j] + rb * r);
+          put(streaming, rs, idx, r);
+          put(streaming, rn, idx, uv[j] + rb * r);
         }
       }
     }
