@@ -97,19 +97,35 @@ def _per_kernel(rows, counter):
     return acc
 
 
-def traffic_summary(fetch_dir, write_dir, substr, copy_bytes, command):
-    fetch = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
-    write = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
-    copy_f = [v for k, vs in fetch.items() if "copy" in k.lower() for v in vs]
-    copy_w = [v for k, vs in write.items() if "copy" in k.lower() for v in vs]
-    if not copy_f or not copy_w:
+def _calibration_copy(fetch_rows, write_rows, kib):
+    """FETCH_SIZE and WRITE_SIZE of the calibration copy: the copy dispatch
+    whose WRITE_SIZE is closest to its size (other copies of the run, e.g. of
+    whole state arrays, differ in size), and the same dispatch of the FETCH
+    run (both runs issue the same sequence of dispatches)."""
+    def copies(rows, counter):
+        return {r["Dispatch_Id"]: float(r["Counter_Value"]) for r in rows
+                if r["Counter_Name"] == counter and "copy" in r["Kernel_Name"].lower()}
+    w = copies(write_rows, "WRITE_SIZE")
+    f = copies(fetch_rows, "FETCH_SIZE")
+    if not w or not f:
         raise RuntimeError("no calibration copy kernel in the counter runs")
+    d = min(w, key=lambda k: abs(w[k] - kib))
+    if d not in f:
+        raise RuntimeError("calibration copy missing from the FETCH_SIZE run")
+    return f[d], w[d]
+
+
+def traffic_summary(fetch_dir, write_dir, substr, copy_bytes, command):
+    fetch_rows, write_rows = _counter_rows(fetch_dir), _counter_rows(write_dir)
+    fetch = _per_kernel(fetch_rows, "FETCH_SIZE")
+    write = _per_kernel(write_rows, "WRITE_SIZE")
     kib = copy_bytes / 1024.0
-    f_scale = kib / max(copy_f)
-    w_scale = kib / max(copy_w)
+    copy_f, copy_w = _calibration_copy(fetch_rows, write_rows, kib)
+    f_scale = kib / copy_f
+    w_scale = kib / copy_w
     out = [f"command: {command}", f"source_sha256: {source_hash()}",
-           f"calibration: copy of {copy_bytes} bytes reads FETCH_SIZE {max(copy_f):.1f} KiB, "
-           f"WRITE_SIZE {max(copy_w):.1f} KiB -> scale {f_scale:.4f} / {w_scale:.4f}", ""]
+           f"calibration: copy of {copy_bytes:.0f} bytes reads FETCH_SIZE {copy_f:.1f} KiB, "
+           f"WRITE_SIZE {copy_w:.1f} KiB -> scale {f_scale:.4f} / {w_scale:.4f}", ""]
     for name in sorted(fetch):
         if substr not in name:
             continue
