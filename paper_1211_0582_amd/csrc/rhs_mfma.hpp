@@ -788,16 +788,33 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     const int i = tid + NT * it;
     nbv[it] = reinterpret_cast<const uint4*>(a.nbr)[i < kNbrVec ? i : kNbrVec - 1];
   }
-  // Fields of the tile (global reads contiguous per field).
-  constexpr int kLoadIters = (16 * Np + NT - 1) / NT;
+  // Fields of the tile (global reads contiguous per field): one value per
+  // lane and load, or for the split forms with Np a multiple of 4 four
+  // consecutive values of one element per lane (16-byte loads: a quarter of
+  // the load instructions, which bound the split forms' address unit).
+  constexpr bool V4 = SPL && Np % 4 == 0;
+  constexpr int kLoadIters = V4 ? 1 : (16 * Np + NT - 1) / NT;
+  constexpr int kLoad4 = (4 * Np + NT - 1) / NT;
   T tv[kLoadIters][6];
+  u32x4 tv4[V4 ? kLoad4 : 1][6];
+  if constexpr (V4) {
 #pragma unroll
-  for (int it = 0; it < kLoadIters; ++it) {
-    const int idx = tid + NT * it;
-    const bool in = idx < ne * Np;
-    const uint32_t vo = in ? uint32_t(k0 * Np + idx) * sz : kOob;
+    for (int it = 0; it < kLoad4; ++it) {
+      const int i4 = 4 * (tid + NT * it);
+      const uint32_t vo = i4 < ne * Np ? uint32_t(k0 * Np + i4) * sz : kOob;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) tv[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
+      for (int c = 0; c < 6; ++c)
+        tv4[it][c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ru, (int)vo, (int)(uint32_t(c * fs) * sz), 0));
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < kLoadIters; ++it) {
+      const int idx = tid + NT * it;
+      const bool in = idx < ne * Np;
+      const uint32_t vo = in ? uint32_t(k0 * Np + idx) * sz : kOob;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tv[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
+    }
   }
 
   // LDS: geometry, codes, material face records, tables, then the fields.
@@ -826,13 +843,25 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   if constexpr (SPL) {
     // FP32 rows [c][e] (records of 8 nodes, zero past Np), then their
     // head/tail records in the split region (or in place).
+    if constexpr (V4) {
 #pragma unroll
-    for (int it = 0; it < kLoadIters; ++it) {
-      const int idx = tid + NT * it;
-      const int ee = idx / Np, j = idx - ee * Np;
-      if (idx < 16 * Np) {
+      for (int it = 0; it < kLoad4; ++it) {
+        const int i4 = 4 * (tid + NT * it);
+        const int ee = i4 / Np, j = i4 - ee * Np;
+        if (i4 < 16 * Np) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t.su[(c * 16 + ee) * X::RSV + j] = tv[it][c];
+          for (int c = 0; c < 6; ++c) *reinterpret_cast<u32x4*>(&t.su[(c * 16 + ee) * X::RSV + j]) = tv4[it][c];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < kLoadIters; ++it) {
+        const int idx = tid + NT * it;
+        const int ee = idx / Np, j = idx - ee * Np;
+        if (idx < 16 * Np) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) t.su[(c * 16 + ee) * X::RSV + j] = tv[it][c];
+        }
       }
     }
     constexpr int pad = 8 * X::J8 - Np;
