@@ -30,7 +30,8 @@
 //    last-level cache store through streaming stores.
 //  * The split 16-bit forms (split_wave) contract the fields themselves on
 //    16x16x32 MFMAs and apply the metric after each direction's contraction;
-//    fields and fluxes are split into heads and tails once per tile, in LDS.
+//    fields and fluxes are split into heads and tails once per tile, in LDS,
+//    and each wave produces all six components of one row block.
 //  * Tiles are mapped to workgroups so that each of the 8 XCDs gets a
 //    contiguous range of elements (neighbours then share that XCD's L2).
 #pragma once
@@ -170,12 +171,12 @@ enum : int {
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int waves_per_tile() {
   constexpr int RB = MfmaShape<N>::RB;
-  // Four waves from RB = 4 (N = 5) for FP64 / FP32 (measured on MI355X);
-  // from RB = 2 for the split forms, whose flux phase with two waves per
-  // tile (11 flux iterations per lane at N = 5) needs more registers than
-  // one wave per SIMD allows.
-  constexpr int min_rb = MIX == 0 ? 4 : 2;
-  constexpr int d = RB >= min_rb ? 4 : 2;
+  // The split forms' waves each produce all six components of their row
+  // blocks (split_wave): one wave per block (up to 14 at N = 9), or with
+  // kCfgWaves two blocks per wave.
+  if constexpr (MIX != 0) return CFG == kCfgWaves && RB >= 2 ? (RB + 1) / 2 : RB;
+  // Four waves from RB = 4 (N = 5) for FP64 / FP32 (measured on MI355X).
+  constexpr int d = RB >= 4 ? 4 : 2;
   if constexpr (CFG == kCfgWaves) return d == 4 ? 2 : (RB >= 2 ? 4 : 2);
   return d;
 }
@@ -185,12 +186,16 @@ constexpr int waves_per_tile() {
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int row_blocks_first() {
   constexpr int RB = MfmaShape<N>::RB;
-  return waves_per_tile<N, T, MIX, CFG>() == 2 ? RB : (RB + 1) / 2;
+  constexpr int W = waves_per_tile<N, T, MIX, CFG>();
+  if constexpr (MIX != 0) return (RB + W - 1) / W;
+  return W == 2 ? RB : (RB + 1) / 2;
 }
+// (split forms: the waves past the first RB mod W take one block less)
 template <int N, typename T, int MIX, int CFG = kCfgDefault>
 constexpr int row_blocks_second() {
-  return waves_per_tile<N, T, MIX, CFG>() == 2 ? MfmaShape<N>::RB
-                                               : MfmaShape<N>::RB - row_blocks_first<N, T, MIX, CFG>();
+  constexpr int W = waves_per_tile<N, T, MIX, CFG>();
+  if constexpr (MIX != 0) return MfmaShape<N>::RB / W;
+  return W == 2 ? MfmaShape<N>::RB : MfmaShape<N>::RB - row_blocks_first<N, T, MIX, CFG>();
 }
 
 // Whether the last 16-row block, which holds at most 4 nodes (N = 1, 3, 4,
@@ -214,13 +219,13 @@ constexpr size_t mfma_lds_bytes() {
 }
 
 // Whether the MFMA variant is built for (N, T): the LDS tile and the
-// accumulators must fit -- row blocks per wave x 3 x 4 scalars per lane, at
-// most 144 registers, plus for the split forms the per-direction partial
-// products of up to two blocks.
+// accumulators must fit -- row blocks per wave x 3 x 4 scalars per lane (the
+// split forms: x 6, plus one block's per-direction partial products), at
+// most 144 registers.
 template <int N, typename T, int MIX = 0, int CFG = kCfgDefault>
 constexpr bool mfma_supported() {
   constexpr int RBW = row_blocks_first<N, T, MIX, CFG>();
-  constexpr int acc = RBW * 3 * 4 * int(sizeof(T)) / 4 + (MIX ? (RBW < 2 ? RBW : 2) * 12 : 0);
+  constexpr int acc = MIX ? RBW * 6 * 4 + 24 : RBW * 3 * 4 * int(sizeof(T)) / 4;
   return mfma_lds_bytes<N, T, MIX>() <= 160 * 1024 && acc <= 144;
 }
 
@@ -502,115 +507,100 @@ __device__ __attribute__((always_inline)) inline void split_records(const float*
   }
 }
 
-// Contraction of one wave of a split form: H as in mfma_wave; the wave
-// produces row blocks rb0 .. rb0 + RBW - 1, G at a time (Y holds G blocks).
-template <int N, typename H16, int NPROD, int H, int NFI, int RBW, bool PALT, typename Tile, typename Gather,
+// Contraction of one wave of a split form: the wave produces all six
+// components of row blocks rb0 .. rb0 + RBW - 1, one block at a time, so
+// each operator fragment it loads feeds both equations (E: curl H + LIFT fE,
+// H: -curl E + LIFT fH).  Per block and direction d, Y = D_d [H; E] (six
+// partial products), folded as out_E += m_d x Y_H and out_H -= m_d x Y_E.
+template <int N, typename H16, int NPROD, int NFI, int RBW, bool PALT, typename Tile, typename Gather,
           typename FluxStep, typename FluxPut, typename FluxStore>
 __device__ __attribute__((always_inline)) inline void split_wave(const RhsArgs& a, Tile& t, const float (&mr)[9],
-                                                                 int lane, int rb0, f32x4 (&out)[RBW][3],
+                                                                 int lane, int rb0, f32x4 (&out)[RBW][6],
                                                                  Gather&& gather, FluxStep&& flux_step,
                                                                  FluxPut&& flux_put, FluxStore&& flux_store) {
   using X = SplitShape<N>;
   using MM = Mfma32<H16>;
   using v8 = typename MM::v8;
   constexpr int KV = X::KV, KL = X::KL, ST = X::ST, J8 = X::J8, J8F = X::J8F, RSV = X::RSV, RSF = X::RSF;
-  constexpr int G = RBW < 2 || RBW > 4 ? 1 : 2;  // row blocks per pass
-  constexpr int NG = (RBW + G - 1) / G;     // passes
-  constexpr int NVS = NG * 3 * KV;          // volume steps of this wave (pass, direction, depth)
-  constexpr int NS = NVS + NG * KL;         // then the lift steps (pass, depth)
+  constexpr int NVS = RBW * 3 * KV;         // volume steps of this wave (block, direction, depth)
+  constexpr int NS = NVS + RBW * KL;        // then the lift steps (block, depth)
   const int e = lane & 15, q = lane >> 4;
   const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.ops_frag16, uint32_t(X::frag_bytes));
 
-  // Operator fragments (head, tail) of step s for block gi of its pass,
-  // prefetched kPre steps ahead: two with up to four row blocks per wave,
-  // one beyond, where the registers are short (PALT: the other depth).  The
-  // lift's first fragments are issued once the fluxes are in registers and
-  // the gathered traces are dead, so that none is held through the flux phase.
-  constexpr int kPreD = RBW <= 4 ? 2 : 1;
-  constexpr int kPre = PALT ? 3 - kPreD : kPreD;
-  auto frag_of = [&](int s, int gi, v8& hi, v8& lo) {
-    const int g = s < NVS ? s / (3 * KV) : (s - NVS) / KL;
-    const int st = s < NVS ? s % (3 * KV) : 3 * KV + (s - NVS) % KL;
-    const int ib = rb0 + g * G + gi;
-    const uint32_t off = uint32_t(((ib * ST + st) * 2 * 64 + lane) * 16);
-    hi = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 0, 0));
-    if constexpr (NPROD >= 2)
-      lo = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 64 * 16, 0));
-  };
-  v8 Ahi[kPre + 1][G], Alo[kPre + 1][G];
+  // Operator fragments (head, tail) of step s, prefetched kPre steps ahead
+  // (two; PALT: one).  The lift's first fragments are issued once the fluxes
+  // are in registers and the gathered traces are dead, so that none is held
+  // through the flux phase.
+  constexpr int kPre = PALT ? 1 : 2;
+  v8 Ahi[kPre + 1], Alo[kPre + 1];
   auto fetch = [&](int s) {
     if (s < NS) {
-      const int g = s < NVS ? s / (3 * KV) : (s - NVS) / KL;
-#pragma unroll
-      for (int gi = 0; gi < G; ++gi)
-        if (g * G + gi < RBW) frag_of(s, gi, Ahi[s % (kPre + 1)][gi], Alo[s % (kPre + 1)][gi]);
+      const int ib = rb0 + (s < NVS ? s / (3 * KV) : (s - NVS) / KL);
+      const int st = s < NVS ? s % (3 * KV) : 3 * KV + (s - NVS) % KL;
+      const uint32_t off = uint32_t(((ib * ST + st) * 2 * 64 + lane) * 16);
+      Ahi[s % (kPre + 1)] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 0, 0));
+      if constexpr (NPROD >= 2)
+        Alo[s % (kPre + 1)] =
+            __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rf, (int)off, 64 * 16, 0));
     }
   };
 #pragma unroll
   for (int s = 0; s < kPre; ++s) fetch(s);
 
-  // B operands of one step: the record of each component for this lane's
+  // B operands of one step for component c: the record of this lane's
   // element and depth group (records past the row's end are clamped: the
   // operator columns there are zero, and the clamped record is finite).
-  auto b_of = [&](const float* row0, int rs, int rec, v8 (&bh)[3], v8 (&bl)[3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float* p = row0 + (c * 16 + e) * rs + 8 * rec;
-      bh[c] = *reinterpret_cast<const v8*>(p);
-      if constexpr (NPROD >= 3) bl[c] = *reinterpret_cast<const v8*>(p + 4);
-    }
+  auto b_of = [&](const float* row0, int rs, int rec, int c, v8& bh, v8& bl) {
+    const float* p = row0 + (c * 16 + e) * rs + 8 * rec;
+    bh = *reinterpret_cast<const v8*>(p);
+    if constexpr (NPROD >= 3) bl = *reinterpret_cast<const v8*>(p + 4);
   };
-  auto mma = [&](int s, int g, const v8 (&bh)[3], const v8 (&bl)[3], f32x4 (&acc)[G][3], bool first) {
-    const int slot = s % (kPre + 1);
-#pragma unroll
-    for (int gi = 0; gi < G; ++gi)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (g * G + gi >= RBW) continue;
-        f32x4 y = MM::mac(Ahi[slot][gi], bh[c], first ? f32x4{0, 0, 0, 0} : acc[gi][c]);
-        if constexpr (NPROD >= 2) y = MM::mac(Alo[slot][gi], bh[c], y);
-        if constexpr (NPROD >= 3) y = MM::mac(Ahi[slot][gi], bl[c], y);
-        acc[gi][c] = y;
-      }
+  auto mac = [&](int slot, const v8& bh, const v8& bl, f32x4 c0) {
+    f32x4 y = MM::mac(Ahi[slot], bh, c0);
+    if constexpr (NPROD >= 2) y = MM::mac(Alo[slot], bh, y);
+    if constexpr (NPROD >= 3) y = MM::mac(Ahi[slot], bl, y);
+    return y;
   };
 
-  // Volume: Y = D_d V per pass and direction, then out += m_d x Y with the
-  // role's sign (V = H for the E equations, -E for the H equations).
-  constexpr int vb = H ? 0 : 3;
-  const float vs = H ? -1.f : 1.f;
-  const float* fv = t.su + X::SPLIT + vb * 16 * RSV;
-  f32x4 Y[G][3];
+  // Volume: Y[c] = D_d of field (c + 3) mod 6, i.e. Y[0..2] from H, Y[3..5]
+  // from E.
+  const float* fv = t.su + X::SPLIT;
+  f32x4 Y[6];
 #pragma unroll
   for (int s = 0; s < NVS; ++s) {
     if (s + kPre < NVS) fetch(s + kPre);
-    const int g = s / (3 * KV), d = (s / KV) % 3, ks = s % KV;
+    const int ib = s / (3 * KV), d = (s / KV) % 3, ks = s % KV;
     const int rec = 4 * ks + q < J8 ? 4 * ks + q : J8 - 1;
     // Each direction reads its operands afresh: shared with the other
-    // directions they would keep all three partial products live at once.
+    // directions they would keep all three directions' Y live at once.
     if (ks == 0 && s > 0) asm volatile("" ::: "memory");
-    v8 bh[3], bl[3];
-    b_of(fv, RSV, rec, bh, bl);
-    mma(s, g, bh, bl, Y, ks == 0);
+    const int slot = s % (kPre + 1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      v8 bh, bl;
+      b_of(fv, RSV, rec, c < 3 ? c + 3 : c - 3, bh, bl);
+      Y[c] = mac(slot, bh, bl, ks == 0 ? f32x4{0, 0, 0, 0} : Y[c]);
+    }
     if (ks == KV - 1) {
-      const float mx = vs * mr[3 * d], my = vs * mr[3 * d + 1], mz = vs * mr[3 * d + 2];
+      const float mx = mr[3 * d], my = mr[3 * d + 1], mz = mr[3 * d + 2];
 #pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        const int ib = g * G + gi;
-        if (ib >= RBW) continue;
+      for (int r = 0; r < 4; ++r) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float c0 = my * Y[gi][2][r] - mz * Y[gi][1][r];
-          const float c1 = mz * Y[gi][0][r] - mx * Y[gi][2][r];
-          const float c2 = mx * Y[gi][1][r] - my * Y[gi][0][r];
-          out[ib][0][r] = d == 0 ? c0 : out[ib][0][r] + c0;
-          out[ib][1][r] = d == 0 ? c1 : out[ib][1][r] + c1;
-          out[ib][2][r] = d == 0 ? c2 : out[ib][2][r] + c2;
+        for (int hh = 0; hh < 2; ++hh) {
+          const float sg = hh ? -1.f : 1.f;
+          const f32x4* y = Y + 3 * hh;
+          const float c0 = sg * (my * y[2][r] - mz * y[1][r]);
+          const float c1 = sg * (mz * y[0][r] - mx * y[2][r]);
+          const float c2 = sg * (mx * y[1][r] - my * y[0][r]);
+          out[ib][3 * hh + 0][r] = d == 0 ? c0 : out[ib][3 * hh + 0][r] + c0;
+          out[ib][3 * hh + 1][r] = d == 0 ? c1 : out[ib][3 * hh + 1][r] + c1;
+          out[ib][3 * hh + 2][r] = d == 0 ? c2 : out[ib][3 * hh + 2][r] + c2;
         }
-        // The fold completes here, before the next direction's operands are
-        // read, so that only one direction's partial products are live.
-#pragma unroll
-        for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(out[ib][c]));
       }
+      // The fold completes here, before the next direction's operands are
+      // read, so that only one direction's partial products are live.
+#pragma unroll
+      for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(out[ib][c]));
     }
   }
   if constexpr (X::INPLACE) {
@@ -644,17 +634,18 @@ __device__ __attribute__((always_inline)) inline void split_wave(const RhsArgs& 
 
   // Lifting: the fluxes' head/tail records written by the workgroup.
   __syncthreads();
-  constexpr int cb = H ? 3 : 0;
-  const float* fq = t.su + cb * 16 * RSF;
 #pragma unroll
   for (int s = NVS; s < NS; ++s) {
     fetch(s + kPre);
-    const int g = (s - NVS) / KL, ls = (s - NVS) % KL;
+    const int ib = (s - NVS) / KL, ls = (s - NVS) % KL;
     const int rec = 4 * ls + q < J8F ? 4 * ls + q : J8F - 1;
-    v8 bh[3], bl[3];
-    b_of(fq, RSF, rec, bh, bl);
-    auto& acc = *reinterpret_cast<f32x4(*)[G][3]>(&out[g * G]);
-    mma(s, g, bh, bl, acc, false);
+    const int slot = s % (kPre + 1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      v8 bh, bl;
+      b_of(t.su, RSF, rec, c, bh, bl);
+      out[ib][c] = mac(slot, bh, bl, out[ib][c]);
+    }
   }
 }
 
@@ -683,8 +674,9 @@ constexpr bool lift_split() {
   return CFG == kCfgLift ? (MIX == 0 && !d) : d;
 }
 
-// Workgroup = two or four waves sharing one tile of 16 elements; wave role
-// h = 0 produces the E equations, h = 1 the H equations (see mfma_wave).
+// Workgroup = the waves sharing one tile of 16 elements: for FP64 / FP32 two
+// or four, wave role h = 0 producing the E equations, h = 1 the H equations
+// (see mfma_wave); for the split forms one per row block (see split_wave).
 // MIX = 0: contraction in T on 16x16x4 MFMAs; MIX = 1..3: T = float with the
 // contraction split in BF16 (NPROD = MIX) on 16x16x32 MFMAs (split_wave);
 // MIX = 4..6: split in FP16 (NPROD = MIX - 3).
@@ -719,7 +711,11 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   const int lane = tid & 63;
   const int h = (tid >> 6) & 1;       // 0: E equations, 1: H equations
   const int rh = tid >> 7;            // row-block half (four waves per tile)
-  const int rb0 = rh * RBW;
+  // Split forms: wave w owns all six components of its row blocks, the
+  // first RB mod W waves one block more than the others.
+  constexpr int SRM = S::RB % WPT;
+  const int sw = tid >> 6;
+  const int rb0 = SPL ? (sw < SRM || SRM == 0 ? sw * RBW : SRM * RBW + (sw - SRM) * RBW1) : rh * RBW;
   const int e = lane & 15, q = lane >> 4;
   const int64_t k0 = tile * 16;
   const int ne = int((a.K - k0) < 16 ? (a.K - k0) : 16);
@@ -1053,14 +1049,18 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
 
   constexpr bool IL = flux_interleaved<N, T, MIX, CFG>();
   static_assert(WPT == 2 || (!IL && !LIFT_HALF), "interleaved flux and split lift assume 128 lanes per tile");
-  acc_t acc[RBW][3];
+  // Output groups of the epilogue: the two roles with three components each,
+  // or for the split forms one group of all six components.
+  constexpr int CPG = SPL ? 6 : 3;
+  acc_t acc[RBW][CPG];
   using B0 = std::integral_constant<int, RBW>;
   using B1 = std::integral_constant<int, RBW1>;
   // The waves of a role run one copy of the wave code when they own equal
   // numbers of row blocks and no 4-row tail, else one copy each.
   constexpr bool TAIL = mfma_tail<N, T, MIX, CFG>();
-  constexpr bool ONE_COPY = WPT == 2 || (!TAIL && RBW1 == RBW);
-  const int nb = (WPT == 2 || rh == 0) ? RBW : RBW1;  // row blocks of this wave
+  constexpr bool ONE_COPY = SPL ? RBW1 == RBW : (WPT == 2 || (!TAIL && RBW1 == RBW));
+  const bool first_blocks = SPL ? (sw < SRM || SRM == 0) : (WPT == 2 || rh == 0);
+  const int nb = first_blocks ? RBW : RBW1;  // row blocks of this wave
   if constexpr (MIX == 0) {
     auto role = [&](auto tw, auto blocks) {
       constexpr bool TW = decltype(tw)::value;
@@ -1080,32 +1080,30 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         role(std::false_type{}, B0{});
     }
   } else {
-    auto role = [&](auto blocks) {
-      constexpr int NB = decltype(blocks)::value;
-      auto& ac = reinterpret_cast<acc_t(&)[NB][3]>(acc);
-      if (h == 0)
-        split_wave<N, H16, NPROD, 0, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
-                                                           flux_put, flux_store);
-      else
-        split_wave<N, H16, NPROD, 1, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step,
-                                                           flux_put, flux_store);
+    auto blocks = [&](auto nbk) {
+      constexpr int NB = decltype(nbk)::value;
+      auto& ac = reinterpret_cast<acc_t(&)[NB][6]>(acc);
+      split_wave<N, H16, NPROD, kFluxIters, NB, PALT>(a, t, mr, lane, rb0, ac, gather, flux_step, flux_put,
+                                                      flux_store);
     };
     if constexpr (ONE_COPY) {
-      role(B0{});
+      blocks(B0{});
     } else {
-      if (rh == 1)
-        role(B1{});
+      if (first_blocks)
+        blocks(B0{});
       else
-        role(B0{});
+        blocks(B1{});
     }
   }
 
-  // Epilogue through LDS: [c][e][i] for the role's three fields (the waves
-  // of one role fill disjoint row blocks), then contiguous stores per field,
-  // shared by the WPT / 2 waves of the role.
+  // Epilogue through LDS: [c][e][i] for the group's fields (the role's
+  // three, or all six for the split forms; the waves of a group fill
+  // disjoint row blocks), then contiguous stores per field, shared by the
+  // group's waves.
   const int nv = ne * Np;
-  constexpr int kRoleLanes = 64 * (WPT / 2);
-  const int rl = lane + 64 * rh;      // lane within the role
+  constexpr int kRoleLanes = SPL ? NT : 64 * (WPT / 2);
+  const int rl = SPL ? tid : lane + 64 * rh;   // lane within the group
+  const int gf = SPL ? 0 : 3 * h;              // the group's first field
   // Output traffic in 16-byte accesses of V consecutive values per lane: a
   // tile's run of a field is 16 Np values, 16-byte aligned (fields start on
   // 256-byte boundaries and 16 Np sizeof(T) is a multiple of 16).
@@ -1118,7 +1116,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // earlier items.  The field offset depends on the role (a per-lane value to
   // the compiler), so it goes into the vector offset: a per-lane scalar
   // offset would make every load a waterfall loop.
-  constexpr int kItems = 3 * kOutIters;
+  constexpr int kItems = CPG * kOutIters;
   constexpr int kAheadRegs = sizeof(T) == 8 ? 112 : 40;  // VGPRs given to loads in flight
   constexpr int kAhead = RK ? (kItems * 8 <= kAheadRegs ? kItems : kAheadRegs / 8) : 0;
   VT rv[RK ? kItems : 1], uv[RK ? kItems : 1];
@@ -1132,7 +1130,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   auto rk_load = [&](int j) {
     const int c = j / kOutIters, it = j % kOutIters;
     const int idx = V * (rl + kRoleLanes * it);
-    const uint32_t vo = idx < nv ? uint32_t((3 * h + c) * fs + k0 * Np + idx) * sz : kOob;
+    const uint32_t vo = idx < nv ? uint32_t((gf + c) * fs + k0 * Np + idx) * sz : kOob;
     // the residual is read once per stage: a non-temporal load (cache policy
     // NT) keeps it from displacing neighbour traces in L2 (stage -1 to -2%)
     rv[j] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(rr, (int)vo, 0, 2));
@@ -1141,13 +1139,13 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
 #pragma unroll
   for (int j = 0; j < kAhead; ++j) rk_load(j);
   __syncthreads();
-  T* so = t.su + h * (3 * 16 * Np);
+  T* so = t.su + gf * (16 * Np);
   T* discard = t.su + 6 * 16 * Np + 4 * lane;
   const bool tail_wave = TAIL && rb0 + nb == RB;
 #pragma unroll
   for (int ib = 0; ib < RBW; ++ib)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < CPG; ++c) {
       if (ib >= nb) continue;
       if (ib == nb - 1 && tail_wave) {
         // 4-row block: FP64 row q in component 0; FP32 rows r, reduced over
@@ -1183,12 +1181,12 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // Stores go through one buffer resource per output field that covers just
   // the field's K Np values: the 16-byte store that straddles the end of a
   // ragged last tile loses its out-of-range dwords (the range check is per
-  // dword), so no store sits behind a per-value branch.  The role is
+  // dword), so no store sits behind a per-value branch.  The group is
   // wave-uniform, which makes the resources scalar.
-  const int hu = __builtin_amdgcn_readfirstlane(h);
+  const int gfu = __builtin_amdgcn_readfirstlane(gf);
   typedef uint32_t w32x4 __attribute__((ext_vector_type(4)));
   auto field_rsrc = [&](void* base, int c) {
-    return make_rsrc(static_cast<T*>(base) + (3 * hu + c) * fs, uint32_t(a.K) * Np * sz);
+    return make_rsrc(static_cast<T*>(base) + (gfu + c) * fs, uint32_t(a.K) * Np * sz);
   };
   auto put = [&](auto streaming, __amdgpu_buffer_rsrc_t r, int idx, VT v) {
     const uint32_t vo = idx < nv ? uint32_t(k0 * Np + idx) * sz : kOob;
@@ -1198,7 +1196,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   auto out = [&](auto streaming) {
     if constexpr (!RK) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < CPG; ++c) {
         VT ov[kOutIters];
 #pragma unroll
         for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
@@ -1209,7 +1207,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     } else {
       const T ra = T(a.rk_a), rb = T(a.rk_b), dt = T(a.rk_dt);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < CPG; ++c) {
         VT ov[kOutIters];
 #pragma unroll
         for (int it = 0; it < kOutIters; ++it) ov[it] = so_at(c, it);
