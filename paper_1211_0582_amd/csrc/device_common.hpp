@@ -43,7 +43,7 @@ struct RhsArgs {
   const void* mat;        // K x kMatStride material records, or nullptr (eps = mu = 1)
   const void* ops;        // Dr^T, Ds^T, Dt^T (Np x Np each, [j][i]), LIFT^T (4Nfp x Np, [m][i])
   const void* ops_frag;   // [Dr|Ds|Dt|LIFT] as 16x4 MFMA A-fragments [row block][depth step][lane]
-  const void* ops_frag16; // same operator split into 16-bit heads and tails, 16x16x16 A-fragments
+  const void* ops_frag16; // same operator split into 16-bit heads and tails, 16x16x32 A-fragments
   const uint8_t* nbr;     // 4 x 24 x Nfp neighbour volume node per (face, code, j)
   const int32_t* fmask;   // 4 x Nfp
   int64_t K;
