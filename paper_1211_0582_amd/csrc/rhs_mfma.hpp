@@ -919,6 +919,12 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   const T alpha = T(a.alpha);
   T gx[kFluxIters][6];
   T ox[OWNG ? kFluxIters : 1][6];
+  // Gathers of traces that lie in the tile read LDS (measured on MI355X:
+  // FP32 N = 5 stage -2.8%, FP64 N = 4 -8%, f16x3 N = 5 -1.3%; FP32 at
+  // N = 4, whose two-wave tiles take 8 flux iterations per lane, +5%, and
+  // every precision at N <= 3 3-9% slower).  Not with the split forms'
+  // in-place records, which replace the FP32 rows.
+  constexpr bool LOCAL = !OWNG && N >= 4 && !(sizeof(T) == 4 && MIX == 0 && N == 4);
   T fl[kFluxIters][6];
   auto gather = [&](int it0 = 0, int it1 = 1 << 20) {
 #pragma unroll
@@ -929,13 +935,30 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       pair_of(pr, ee, m);
       const int f = m / Nfp, jj = m - f * Nfp;
       const int32_t cf = (pr < kPairs) ? t.code[4 * ee + f] : -1;
-      // interior: neighbour node; boundary: own node (mirror applied below); dead: zero
+      // interior: neighbour node; boundary: own node (mirror applied below); dead: zero.
+      // With LOCAL a trace of an element of the tile (the own node on a
+      // wall, or a neighbour inside the tile) comes from the field tile in
+      // LDS, the others from global memory.
       uint32_t vo = kOob;
-      if (pr < kPairs && ee < ne)
-        vo = uint32_t(cf >= 0 ? int64_t(cf >> 5) * Np + t.nbr[(f * 24 + (cf & 31)) * Nfp + jj]
-                              : (k0 + ee) * Np + t.fmask[m]) * sz;
+      bool local = false;
+      int le = 0, ln = 0;   // element in the tile, node
+      if (pr < kPairs && ee < ne) {
+        const int64_t nk = cf >= 0 ? int64_t(cf >> 5) : k0 + ee;
+        const int nn = cf >= 0 ? int(t.nbr[(f * 24 + (cf & 31)) * Nfp + jj]) : int(t.fmask[m]);
+        local = LOCAL && nk >= k0 && nk < k0 + ne;
+        le = int(nk - k0);
+        ln = nn;
+        if (!local) vo = uint32_t(nk * Np + nn) * sz;
+      }
 #pragma unroll
       for (int c = 0; c < 6; ++c) gx[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
+      if constexpr (LOCAL) {
+        if (local) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c)
+            gx[it][c] = SPL ? t.su[(c * 16 + le) * X::RSV + ln] : t.su[(c * Np4 + ln) * TS + le];
+        }
+      }
       if constexpr (OWNG) {
         const uint32_t oo = (pr < kPairs && ee < ne) ? uint32_t((k0 + ee) * Np + t.fmask[m]) * sz : kOob;
 #pragma unroll
