@@ -87,6 +87,33 @@ struct Mfma16<double> {
   }
 };
 
+// x / D for 0 <= x < XMAX as (x R) >> S with a 24-bit multiply: full rate on
+// the vector ALU, where a 32-bit division by a constant takes a quarter-rate
+// multiply-high and a 32-bit multiply-add a quarter-rate 64-bit one.  S is the
+// smallest shift that is exact over the range, checked at compile time.
+template <int D, int XMAX>
+struct SmallDiv {
+  static constexpr bool exact(int s) {
+    const unsigned long long r = ((1ull << s) + D - 1) / D;
+    if (r >= (1u << 24) || (unsigned long long)XMAX * r >= (1ull << 32)) return false;
+    for (int x = 0; x < XMAX; ++x)
+      if (int((unsigned long long)x * r >> s) != x / D) return false;
+    return true;
+  }
+  static constexpr int shift() {
+    for (int s = 8; s <= 24; ++s)
+      if (exact(s)) return s;
+    return -1;
+  }
+  static constexpr int S = shift();
+  static_assert(S > 0, "no exact 24-bit reciprocal for this range");
+  static constexpr unsigned R = unsigned(((1ull << S) + D - 1) / D);
+  __device__ static inline int div(int x) { return int(unsigned(__umul24(unsigned(x), R)) >> S); }
+};
+
+// 24-bit product (both factors below 2^24): one full-rate instruction.
+__device__ inline int mul24(int a, int b) { return __umul24(unsigned(a), unsigned(b)); }
+
 template <int N>
 struct MfmaShape {
   static constexpr int Np = Order<N>::Np, Nfp = Order<N>::Nfp, NF = Order<N>::NF;
@@ -845,8 +872,10 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         const int i4 = 4 * (tid + NT * it);
         const int ee = i4 / Np, j = i4 - ee * Np;
         if (i4 < 16 * Np) {
+          int o = ee * X::RSV + j;
+          asm("" : "+v"(o));  // one address, constant offsets per component
 #pragma unroll
-          for (int c = 0; c < 6; ++c) *reinterpret_cast<u32x4*>(&t.su[(c * 16 + ee) * X::RSV + j]) = tv4[it][c];
+          for (int c = 0; c < 6; ++c) *reinterpret_cast<u32x4*>(&t.su[o + c * 16 * X::RSV]) = tv4[it][c];
         }
       }
     } else {
@@ -855,8 +884,10 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         const int idx = tid + NT * it;
         const int ee = idx / Np, j = idx - ee * Np;
         if (idx < 16 * Np) {
+          int o = ee * X::RSV + j;
+          asm("" : "+v"(o));
 #pragma unroll
-          for (int c = 0; c < 6; ++c) t.su[(c * 16 + ee) * X::RSV + j] = tv[it][c];
+          for (int c = 0; c < 6; ++c) t.su[o + c * 16 * X::RSV] = tv[it][c];
         }
       }
     }
@@ -875,8 +906,10 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       const int idx = tid + NT * it;
       const int ee = idx / Np, j = idx - ee * Np;
       if (idx < 16 * Np) {
+        int o = j * TS + ee;
+        asm("" : "+v"(o));  // one address, constant offsets per component
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t.su[(c * Np4 + j) * TS + ee] = tv[it][c];
+        for (int c = 0; c < 6; ++c) t.su[o + c * Np4 * TS] = tv[it][c];
       }
     }
     if constexpr (Np4 > Np) {
@@ -909,8 +942,8 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // flux iterations over face-node rows.
   auto pair_of = [&](int pr, int& ee, int& m) {
     if constexpr (!LIFT_HALF) {
-      ee = pr / NF;
-      m = pr - ee * NF;
+      ee = SmallDiv<NF, NT * kFluxIters>::div(pr);
+      m = pr - mul24(ee, NF);
     } else {
       ee = pr & 15;
       m = pr >> 4;
@@ -926,6 +959,12 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   // in-place records, which replace the FP32 rows.
   constexpr bool LOCAL = !OWNG && N >= 4 && !(sizeof(T) == 4 && MIX == 0 && N == 4);
   T fl[kFluxIters][6];
+  // LDS index of a local trace (component 0), -1 for a gathered one.  The
+  // LDS reads wait until flux_step: issued here they would overwrite
+  // registers whose global loads are still in flight (the load of a local
+  // lane is a null load), and the wait for those loads would serialise the
+  // gather iterations.
+  int loc[LOCAL ? kFluxIters : 1];
   auto gather = [&](int it0 = 0, int it1 = 1 << 20) {
 #pragma unroll
     for (int it = 0; it < kFluxIters; ++it) {
@@ -933,7 +972,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       const int pr = tid + NT * it;
       int ee, m;
       pair_of(pr, ee, m);
-      const int f = m / Nfp, jj = m - f * Nfp;
+      const int f = SmallDiv<Nfp, NF>::div(m), jj = m - mul24(f, Nfp);
       const int32_t cf = (pr < kPairs) ? t.code[4 * ee + f] : -1;
       // interior: neighbour node; boundary: own node (mirror applied below); dead: zero.
       // With LOCAL a trace of an element of the tile (the own node on a
@@ -943,22 +982,17 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       bool local = false;
       int le = 0, ln = 0;   // element in the tile, node
       if (pr < kPairs && ee < ne) {
-        const int64_t nk = cf >= 0 ? int64_t(cf >> 5) : k0 + ee;
-        const int nn = cf >= 0 ? int(t.nbr[(f * 24 + (cf & 31)) * Nfp + jj]) : int(t.fmask[m]);
-        local = LOCAL && nk >= k0 && nk < k0 + ne;
-        le = int(nk - k0);
+        // element relative to the tile (32-bit: element indices are below 2^26)
+        const int dk = cf >= 0 ? int(int64_t(cf >> 5) - k0) : ee;
+        const int nn = cf >= 0 ? int(t.nbr[mul24(f, 24 * Nfp) + mul24(cf & 31, Nfp) + jj]) : int(t.fmask[m]);
+        local = LOCAL && unsigned(dk) < unsigned(ne);
+        le = dk;
         ln = nn;
-        if (!local) vo = uint32_t(nk * Np + nn) * sz;
+        if (!local) vo = ((uint32_t(k0) + uint32_t(dk)) * uint32_t(Np) + uint32_t(nn)) * sz;
       }
 #pragma unroll
       for (int c = 0; c < 6; ++c) gx[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
-      if constexpr (LOCAL) {
-        if (local) {
-#pragma unroll
-          for (int c = 0; c < 6; ++c)
-            gx[it][c] = SPL ? t.su[(c * 16 + le) * X::RSV + ln] : t.su[(c * Np4 + ln) * TS + le];
-        }
-      }
+      if constexpr (LOCAL) loc[it] = local ? (SPL ? le * X::RSV + ln : ln * TS + le) : -1;
       if constexpr (OWNG) {
         const uint32_t oo = (pr < kPairs && ee < ne) ? uint32_t((k0 + ee) * Np + t.fmask[m]) * sz : kOob;
 #pragma unroll
@@ -977,7 +1011,13 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
     int ee, m;
     pair_of(pr, ee, m);
     if (pr < kPairs) {
-      const int f = m / Nfp;
+      if constexpr (LOCAL) {
+        if (loc[it] >= 0) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) gx[it][c] = t.su[loc[it] + c * (SPL ? 16 * X::RSV : Np4 * TS)];
+        }
+      }
+      const int f = SmallDiv<Nfp, NF>::div(m);
       const int own = t.fmask[m];
       // exterior state E+ = se g, H+ = sh g with g the gathered trace
       // (interior: the neighbour's, se = sh = 1; boundary: the own one)
@@ -1028,8 +1068,10 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       int ee, m;
       pair_of(pr, ee, m);
       if (pr < kPairs) {
+        int o = ee * X::RSF + m;
+        asm("" : "+v"(o));  // one address, constant offsets (as in flux_store)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t.su[(c * 16 + ee) * X::RSF + m] = fl[it][c];
+        for (int c = 0; c < 6; ++c) t.su[o + c * 16 * X::RSF] = fl[it][c];
       }
     }
   };
@@ -1064,8 +1106,13 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       int ee, m;
       pair_of(pr, ee, m);
       if (it >= it0 && it < it1 && pr < kPairs) {
+        // One address per pair, the components at constant offsets (left
+        // to itself the compiler merges m = pr - NF ee into each component's
+        // row index and spends three integer instructions per store).
+        int o = (m - base) * TQ + ee;
+        asm("" : "+v"(o));
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t.su[(c * FR + m - base) * TQ + ee] = fl[it][c];
+        for (int c = 0; c < 6; ++c) t.su[o + c * FR * TQ] = fl[it][c];
       }
     }
   };
