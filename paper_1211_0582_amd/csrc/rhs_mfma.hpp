@@ -503,11 +503,21 @@ struct Mfma32<_Float16> {
 
 template <typename H16>
 __device__ inline void split8(const float (&x)[8], typename Mfma32<H16>::v8& hi, typename Mfma32<H16>::v8& lo) {
+  // Pairs: one packed conversion per head pair, widened back from the packed
+  // value (elementwise, the compiler converts each head twice: once alone
+  // for the tail, once packed for the store).
+  typedef H16 h2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const H16 h = static_cast<H16>(x[v]);
-    hi[v] = h;
-    lo[v] = static_cast<H16>(x[v] - static_cast<float>(h));
+  for (int v = 0; v < 8; v += 2) {
+    const f2 xv = {x[v], x[v + 1]};
+    const h2 h = __builtin_convertvector(xv, h2);
+    const f2 b = __builtin_convertvector(h, f2);
+    const h2 l = __builtin_convertvector(f2{xv[0] - b[0], xv[1] - b[1]}, h2);
+    hi[v] = h[0];
+    hi[v + 1] = h[1];
+    lo[v] = l[0];
+    lo[v + 1] = l[1];
   }
 }
 
@@ -521,8 +531,8 @@ __device__ __attribute__((always_inline)) inline void split_records(const float*
   for (int it = 0; it < (n + NT - 1) / NT; ++it) {
     const int r = tid + NT * it;
     if (r < n) {
-      const int row = r / J, j8 = r - row * J;
-      const int o = row * RS + 8 * j8;
+      const int row = SmallDiv<J, NT * ((n + NT - 1) / NT)>::div(r), j8 = r - mul24(row, J);
+      const int o = mul24(row, RS) + 8 * j8;
       const f32x4 a = *reinterpret_cast<const f32x4*>(src + o);
       const f32x4 b = *reinterpret_cast<const f32x4*>(src + o + 4);
       const float x[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
@@ -992,7 +1002,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       }
 #pragma unroll
       for (int c = 0; c < 6; ++c) gx[it][c] = buf_load<T>(ru, vo, uint32_t(c * fs) * sz);
-      if constexpr (LOCAL) loc[it] = local ? (SPL ? le * X::RSV + ln : ln * TS + le) : -1;
+      if constexpr (LOCAL) loc[it] = local ? (SPL ? mul24(le, X::RSV) + ln : ln * TS + le) : -1;
       if constexpr (OWNG) {
         const uint32_t oo = (pr < kPairs && ee < ne) ? uint32_t((k0 + ee) * Np + t.fmask[m]) * sz : kOob;
 #pragma unroll
