@@ -963,11 +963,11 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
   T gx[kFluxIters][6];
   T ox[OWNG ? kFluxIters : 1][6];
   // Gathers of traces that lie in the tile read LDS (measured on MI355X:
-  // FP32 N = 5 stage -2.8%, FP64 N = 4 -8%, f16x3 N = 5 -1.3%; FP32 at
-  // N = 4, whose two-wave tiles take 8 flux iterations per lane, +5%, and
-  // every precision at N <= 3 3-9% slower).  Not with the split forms'
-  // in-place records, which replace the FP32 rows.
-  constexpr bool LOCAL = !OWNG && N >= 4 && !(sizeof(T) == 4 && MIX == 0 && N == 4);
+  // FP32 N = 5 stage -2.8%, FP64 N = 4 -8%, f16x3 N = 5 -1.3%; with the
+  // LDS reads made at the flux step, FP64 N = 1-3 RHS -4 to -5% and FP32
+  // N = 1, 3, 4 -2 to -4%, while the split forms at N <= 3 gain nothing).
+  // Not with the split forms' in-place records, which replace the FP32 rows.
+  constexpr bool LOCAL = !OWNG && (MIX == 0 || N >= 4);
   T fl[kFluxIters][6];
   // LDS index of a local trace (component 0), -1 for a gathered one.  The
   // LDS reads wait until flux_step: issued here they would overwrite
