@@ -916,7 +916,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
       const int idx = tid + NT * it;
       const int ee = idx / Np, j = idx - ee * Np;
       if (idx < 16 * Np) {
-        int o = j * TS + ee;
+        int o = mul24(j, TS) + ee;
         asm("" : "+v"(o));  // one address, constant offsets per component
 #pragma unroll
         for (int c = 0; c < 6; ++c) t.su[o + c * Np4 * TS] = tv[it][c];
@@ -1119,7 +1119,7 @@ __device__ __attribute__((always_inline)) inline void rhs_mfma_tile(const RhsArg
         // One address per pair, the components at constant offsets (left
         // to itself the compiler merges m = pr - NF ee into each component's
         // row index and spends three integer instructions per store).
-        int o = (m - base) * TQ + ee;
+        int o = mul24(m - base, TQ) + ee;
         asm("" : "+v"(o));
 #pragma unroll
         for (int c = 0; c < 6; ++c) t.su[o + c * FR * TQ] = fl[it][c];
